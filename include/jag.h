@@ -1,0 +1,285 @@
+/*
+ * jag.h -- C ABI of the JAG (Joint Attribute Graph) filtered vector search
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper Section 2, "Filtered Nearest Neighbors Search"): each point
+ * p = (x_p, a_p) has a vector x_p in R^d and an attribute a_p; each query
+ * q = (x_q, f_q) has a vector and a filter.  The answer is the k points with
+ * g(a_p, f_q) = 1 nearest to x_q.  The library builds a Threshold-JAG index
+ * (Section 3.3, Algorithms 3 and 4) and answers batches of queries with the
+ * filtered greedy search of Algorithms 1 and 2 on the GPU, ordering
+ * candidates by D_F = (dist_F(f_q, a_u), dist(x_q, x_u)) lexicographically
+ * (Section 3.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns a jag_status; 0 is success.  On failure the call has
+ *    no effect on its outputs beyond what it documents, and jag_last_error()
+ *    returns a thread-local message.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory on the current device (e.g. torch tensors on cuda:0).
+ *  - The caller owns every buffer it passes in; inputs are only read during
+ *    the call (or, for asynchronous calls, until the stream reaches the
+ *    work).  The library owns the jag_index until jag_free.
+ *  - Vector distances are squared Euclidean distances; "dist" below means
+ *    that (it orders candidates exactly like the Euclidean distance).
+ *  - Labels are integers in [0, vocab) with vocab <= 65535; each item's
+ *    label list must be sorted ascending without repeats.
+ *  - One jag_index may be searched from several host threads / streams at
+ *    once; building, loading, saving and freeing must not overlap other use
+ *    of the same index.
+ */
+#ifndef JAG_H
+#define JAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jag_index jag_index; /* opaque, owned by the library */
+
+typedef enum {
+    JAG_OK = 0,
+    JAG_EINVAL = -1,      /* bad argument, shape, filter or label */
+    JAG_ENOMEM = -2,      /* host or device allocation failed */
+    JAG_EDEVICE = -3,     /* HIP runtime error or no gfx950 device */
+    JAG_EIO = -4,         /* file could not be read or written */
+    JAG_EUNSUPPORTED = -5 /* valid request the index cannot serve (e.g. no FP32 copy) */
+} jag_status;
+
+/* Vector store used by the search (Section 8-style precision choices are the
+ * library's own; the paper does not fix a precision). */
+typedef enum {
+    JAG_STORE_F32 = 0,      /* FP32 rows */
+    JAG_STORE_BF16 = 1,     /* BF16 rows, round to nearest even */
+    JAG_STORE_FP8_E4M3 = 2  /* OCP E4M3 rows with one FP32 scale per row */
+} jag_store;
+
+/* Filter types of Section 2 ("Filter Constraints"). */
+typedef enum {
+    JAG_LABEL = 0,   /* item's label set contains `label` (equality for one-label items) */
+    JAG_RANGE = 1,   /* lo <= scalar attribute <= hi (inclusive) */
+    JAG_SUBSET = 2,  /* item's label set contains every label of pool[off, off+len) */
+    JAG_BOOLEAN = 3  /* DNF program in pool[off, off+len): see jag_filter */
+} jag_filter_type;
+
+/* Attribute kinds an index can hold; the threshold list names one per entry. */
+typedef enum { JAG_ATTR_SCALAR = 0, JAG_ATTR_LABELS = 1 } jag_attr_kind;
+
+/* Per-item attributes (host).  Either part may be absent (NULL). */
+typedef struct {
+    const int32_t *scalar;    /* [n] int32 range attribute */
+    const int64_t *label_off; /* [n+1] CSR row offsets into labels */
+    const int32_t *labels;    /* [label_off[n]] label ids */
+    int32_t vocab;            /* label vocabulary size, 1..65535 */
+} jag_attrs;
+
+/* One entry of the threshold list T (Section 3.3; Appendix D.3): the capped
+ * attribute distance uses, for each point p, the `quantile` of dist_A(a_p, .)
+ * over 500 sampled points.  quantile >= 1 means t = +inf (pure vector order),
+ * quantile <= 0 means t = 0 (strict attribute order). */
+typedef struct {
+    int32_t kind;   /* jag_attr_kind */
+    float quantile; /* in [0, 1] */
+} jag_threshold;
+
+typedef struct {
+    int32_t R;                /* out-degree bound ("deg", Algorithm 4), 1..64 */
+    int32_t L_build;          /* beam l_b of the insertion searches (Algorithm 3); 0 = 2R */
+    float alpha;              /* pruning parameter (paper: 1.2) */
+    int32_t n_thr;            /* |T|, 1..8 */
+    const jag_threshold *thr; /* [n_thr] */
+    int32_t store;            /* jag_store used by the search */
+    int32_t keep_f32;         /* also keep an FP32 copy on the device for reranking */
+    uint64_t seed;            /* insertion order and threshold sampling */
+    int32_t n_threads;        /* host builder threads; 0 = all hardware threads */
+    int32_t max_batch;        /* cap on points inserted per parallel round; 0 = max(64, n/50) */
+} jag_build_params;
+
+/*
+ * Query filter (host).  Fields by type:
+ *   LABEL:   label
+ *   RANGE:   lo, hi (inclusive)
+ *   SUBSET:  off, len -> 1..16 required labels in pool
+ *   BOOLEAN: off, len -> DNF program in pool:
+ *              ncl, nlit_1, lit..., nlit_2, lit..., ...
+ *            1..8 clauses, at most 16 literals in all; a literal l >= 0 asks
+ *            for label l, l < 0 asks for the absence of label ~l.  Repeated
+ *            literals count once; a clause holding l and ~l never holds.
+ */
+typedef struct {
+    int32_t type, label, lo, hi, off, len;
+} jag_filter;
+
+/* Bytes of one encoded filter record on the device (see jag_encode_filters). */
+#define JAG_FILTER_RECORD_BYTES 128
+
+/* Ladder of beam widths the learned predictor chooses from. */
+#define JAG_LADDER_MAX 16
+
+typedef struct {
+    int32_t L;           /* beam width l_s (fixed mode), k..1024 */
+    int32_t learned;     /* 0 = fixed beam L; 1 = predicted beam (index needs a predictor);
+                            2 = fixed beam L plus predictor features written to `features` */
+    float delta;         /* learned mode: offset added to the predicted ladder index */
+    int32_t rerank_mult; /* 0 = none; m > 0 rescores the best m*k entries of the final list
+                            from the FP32 copy (needs keep_f32 or an FP32 store); m*k <= 64 */
+    int32_t max_hops;    /* 0 = unlimited; else stop after this many expansions */
+    int32_t *stats;      /* optional device int32 [nq][4]: expansions, vector distances,
+                            attribute evaluations, chosen beam (learned) or L */
+    float *features;     /* learned == 2: device float [nq][16] predictor features */
+} jag_search_params;
+
+typedef struct {
+    int64_t n;
+    int32_t d, R, entry, store, has_f32, has_scalar, has_labels, label_width, vocab;
+    int32_t has_predictor;
+    int64_t device_bytes; /* HBM held by the index */
+} jag_index_info;
+
+/* ---- build, import, persistence -------------------------------------- */
+
+/*
+ * Build a Threshold-JAG index over n host vectors X[n][d] (FP32, row-major)
+ * with attributes A (Algorithms 3 and 4, with the Appendix D.3 notes: a
+ * neighbour picked for an earlier threshold joins later buckets without the
+ * alpha test, and each bucket stops at ceil(0.9 R / |T|)).  Points are
+ * inserted in parallel rounds of growing size; within a round every
+ * insertion searches the graph as it stood before the round, so the result
+ * depends only on the seed, not on the thread count.  The graph, attributes
+ * and vector store are then placed in device memory of the current device.
+ * Errors: EINVAL (n < 1, d < 1, d > 512, bad params or attributes),
+ * ENOMEM, EDEVICE.
+ */
+jag_status jag_build(const float *X, int64_t n, int32_t d, const jag_attrs *A,
+                     const jag_build_params *P, jag_index **out);
+
+/*
+ * The graph construction of jag_build alone, on host threads, with no
+ * device involved: writes adj_out[n][P->R] (host, -1 padded) and the entry
+ * vertex to *entry.  P->store and P->keep_f32 are ignored.  Same errors as
+ * jag_build except EDEVICE.
+ */
+jag_status jag_build_graph(const float *X, int64_t n, int32_t d, const jag_attrs *A,
+                           const jag_build_params *P, int32_t *adj_out, int32_t *entry);
+
+/*
+ * Make an index from a given graph (host adj[n][R], -1 padded, no
+ * repeated ids in a row, ids in [0, n)) and entry vertex, instead of
+ * building one.  Only P->store and P->keep_f32 are read from P (P may be
+ * NULL: FP32 store).  Errors: EINVAL on a malformed graph.
+ */
+jag_status jag_build_from_graph(const float *X, int64_t n, int32_t d, const jag_attrs *A,
+                                const int32_t *adj, int32_t R, int32_t entry,
+                                const jag_build_params *P, jag_index **out);
+
+/* Write / read the index (graph, FP32 vectors, attributes, entry vertex,
+ * store choice, predictor) to / from a versioned file.  jag_load places the
+ * index on the current device.  Errors: EIO, EINVAL (bad file), ENOMEM. */
+jag_status jag_save(const jag_index *idx, const char *path);
+jag_status jag_load(const char *path, jag_index **out);
+
+/* Release the index and its device memory.  NULL is allowed. */
+void jag_free(jag_index *idx);
+
+jag_status jag_info(const jag_index *idx, jag_index_info *out);
+
+/* Copy the graph to host adj_out[n][R] and the entry vertex to *entry. */
+jag_status jag_get_graph(const jag_index *idx, int32_t *adj_out, int32_t *entry);
+
+/* Copy the device vector store to the host, unpadded: F32 -> float[n][d],
+ * BF16 -> uint16[n][d], FP8 -> uint8[n][d] codes plus float[n] scales
+ * (scales_out is only written for FP8 and may be NULL otherwise). */
+jag_status jag_get_store(const jag_index *idx, void *rows_out, float *scales_out);
+
+/* ---- search ------------------------------------------------------------ */
+
+/*
+ * Validate and encode nq host filters into fixed-size records
+ * (records_out, host, nq * JAG_FILTER_RECORD_BYTES bytes), including the
+ * index's selectivity estimate for each filter (exact for LABEL and RANGE;
+ * independence-based for SUBSET and BOOLEAN).  The records may be copied to
+ * the device once and reused by jag_search_encoded.
+ * Errors: EINVAL (unknown type, malformed pool program, label outside
+ * [0, vocab), RANGE on an index without scalars, label filters on an index
+ * without labels, too many labels/literals/clauses).
+ */
+jag_status jag_encode_filters(const jag_index *idx, const jag_filter *F, int64_t nq,
+                              const int32_t *pool, int64_t pool_len, void *records_out);
+
+/*
+ * Filtered greedy search (Algorithm 2 over Algorithm 1) for nq queries,
+ * one GPU wavefront per query.  Q: device float[nq][d].  records: device,
+ * from jag_encode_filters.  Outputs (device): ids[nq][k] valid item ids
+ * (those with dist_F = 0) in increasing (dist, id) order, padded with -1;
+ * dists[nq][k] the matching squared distances (from the FP32 copy when
+ * reranking, else from the store; +inf for padding); count[nq] the number
+ * of valid ids.  Asynchronous on `stream` (a hipStream_t; NULL = default
+ * stream).  Errors: EINVAL (k < 1, k > 64, L < k, L > 1024, bad params),
+ * EUNSUPPORTED (rerank without an FP32 copy, learned without predictor),
+ * EDEVICE.
+ */
+jag_status jag_search_encoded(jag_index *idx, const float *Q, int64_t nq, const void *records,
+                              int32_t k, const jag_search_params *S, int32_t *ids, float *dists,
+                              int32_t *count, void *stream);
+
+/* Convenience: encode host filters, stage them on the device (stream-ordered
+ * allocation on `stream`) and run jag_search_encoded. */
+jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t nq, const jag_filter *F,
+                            const int32_t *pool, int64_t pool_len, int32_t k,
+                            const jag_search_params *S, int32_t *ids, float *dists,
+                            int32_t *count, void *stream);
+
+/*
+ * Exact filtered k-NN on the GPU over the FP32 vectors (needs the FP32
+ * copy): every item passing the filter is scored.  Same output layout as
+ * jag_search_encoded.  This is the Pre-Filtering method (Appendix D.4); the
+ * library uses it to label predictor training data.
+ */
+jag_status jag_exact_knn(jag_index *idx, const float *Q, int64_t nq, const void *records,
+                         int32_t k, int32_t *ids, float *dists, int32_t *count, void *stream);
+
+/* ---- learned beam predictor (not in the paper) -------------------------- */
+
+/*
+ * Attach predictor weights: params = host float[5313] in the layout
+ * W1[64][16] b1[64] W2[64][64] b2[64] w3[64] b3 (stored on the device in
+ * BF16, round to nearest even); ladder = host int32[nladder] increasing
+ * beam widths (nladder <= JAG_LADDER_MAX); the network output y selects
+ * ladder[clamp(ceil(y + delta), 0, nladder-1)]; the search then stops after
+ * ceil(rho * Lhat) expansions.
+ */
+jag_status jag_set_predictor(jag_index *idx, const float *params, int32_t nladder,
+                             const int32_t *ladder, float rho);
+
+/*
+ * Train the predictor on the GPU: minibatch Adam on the mean squared error
+ * between the network output and targets.  features: device float[m][16],
+ * targets: device float[m].  params_inout: host float[5313] (initial values
+ * in, trained values out, FP32).  loss_out: host float[epochs] mean loss of
+ * each epoch (may be NULL).  Synchronous.
+ */
+jag_status jag_train_predictor(const float *features, const float *targets, int64_t m,
+                               float *params_inout, int32_t epochs, int32_t batch, float lr,
+                               uint64_t seed, float *loss_out, void *stream);
+
+/*
+ * One forward/backward pass on the GPU without updating: loss (host) and
+ * gradient grad_out (host float[5313]) of the mean squared error over m
+ * samples for the given FP32 params.  For checking the training kernels.
+ */
+jag_status jag_predictor_grad(const float *features, const float *targets, int64_t m,
+                              const float *params, float *loss_out, float *grad_out,
+                              void *stream);
+
+/* ---- misc ---------------------------------------------------------------- */
+
+const char *jag_last_error(void);
+const char *jag_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JAG_H */

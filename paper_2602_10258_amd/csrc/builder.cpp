@@ -1,0 +1,402 @@
+// Threshold-JAG construction on host threads (paper Section 3.3,
+// Algorithms 3 and 4, Appendix D.3).
+//
+// Insertions run in rounds: the first point (the entry vertex) alone, then
+// rounds that double in size up to a cap.  Within a round every point runs
+// its |T| greedy searches against the graph frozen at the start of the
+// round and prunes its own out-list (Algorithm 3, lines up to the prune);
+// then the reverse edges of the whole round are grouped by target and each
+// target vertex merges its new in-links, re-pruning when it would exceed R.
+// Every write touches one vertex's row from one task, so the graph depends
+// only on the seed, not on thread count or timing.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <thread>
+
+#include "jag_internal.h"
+
+namespace jag {
+namespace {
+
+inline uint64_t mix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+inline float l2sq(const float *__restrict a, const float *__restrict b, int d)
+{
+    float s = 0.f;
+#pragma omp simd reduction(+ : s)
+    for (int i = 0; i < d; i++) {
+        float t = a[i] - b[i];
+        s += t * t;
+    }
+    return s;
+}
+
+void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int)> &fn,
+                  int64_t grain = 1)
+{
+    if (n <= 0) return;
+    if (nthreads <= 1 || n <= grain) {
+        for (int64_t i = 0; i < n; i++) fn(i, 0);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    int nt = (int)std::min<int64_t>(nthreads, (n + grain - 1) / grain);
+    for (int t = 0; t < nt; t++) {
+        th.emplace_back([&, t] {
+            for (;;) {
+                int64_t s = next.fetch_add(grain);
+                if (s >= n) break;
+                int64_t e = std::min(n, s + grain);
+                for (int64_t i = s; i < e; i++) fn(i, t);
+            }
+        });
+    }
+    for (auto &x : th) x.join();
+}
+
+struct Key {
+    float f;   // capped attribute distance
+    float d2;  // squared vector distance
+    int32_t id;
+};
+inline bool key_lt(const Key &a, const Key &b)
+{
+    if (a.f != b.f) return a.f < b.f;
+    if (a.d2 != b.d2) return a.d2 < b.d2;
+    return a.id < b.id;
+}
+
+struct Builder {
+    const float *X;
+    int64_t n;
+    int d;
+    AttrView A;
+    int R, lb, nT, cap;
+    int32_t entry = 0;
+    float alpha2;
+    std::vector<int32_t> kinds;
+    std::vector<float> thr;  // [n][nT]
+    std::vector<int32_t> adj;
+    std::vector<int32_t> deg;
+
+    float dist_a(int kind, int64_t i, int64_t j) const
+    {
+        if (kind == JAG_ATTR_SCALAR) return std::fabs((float)((int64_t)A.scalar[i] - (int64_t)A.scalar[j]));
+        // |a_i XOR a_j| by merging the two sorted rows
+        int64_t x = A.loff[i], xe = A.loff[i + 1], y = A.loff[j], ye = A.loff[j + 1];
+        int64_t common = 0;
+        while (x < xe && y < ye) {
+            if (A.lab[x] == A.lab[y]) {
+                common++;
+                x++;
+                y++;
+            } else if (A.lab[x] < A.lab[y]) x++;
+            else y++;
+        }
+        return (float)((A.loff[i + 1] - A.loff[i]) + (A.loff[j + 1] - A.loff[j]) - 2 * common);
+    }
+    float capped(int ti, int64_t p, int64_t v) const
+    {
+        float t = thr[(size_t)p * nT + ti];
+        if (std::isinf(t)) return 0.f;
+        float x = dist_a(kinds[ti], p, v) - t;
+        return x > 0.f ? x : 0.f;
+    }
+    const float *row(int64_t i) const { return X + (size_t)i * d; }
+};
+
+struct Scratch {
+    std::vector<uint32_t> seen;  // epoch stamps, size n
+    uint32_t epoch = 0;
+    std::vector<Key> L;
+    std::vector<uint8_t> expanded;
+    std::vector<int32_t> visited;
+    std::vector<int32_t> cand;
+    // prune scratch
+    std::vector<float> pd2;
+    std::vector<float> pf;
+    std::vector<int32_t> order;
+    std::vector<uint8_t> chosen_flag;
+    std::vector<int32_t> bucket, chosen;
+};
+
+// GreedySearch(G, x_p, 1, l_b, D_A^t) over the frozen graph; appends the
+// expanded vertices to s.visited.  A vertex seen earlier in this search is
+// not re-evaluated: the beam always holds the l_b best vertices discovered,
+// so one that fell out can never get back in.
+void greedy_build_search(const Builder &B, Scratch &s, int64_t p, int ti)
+{
+    if (++s.epoch == 0) {
+        std::fill(s.seen.begin(), s.seen.end(), 0u);
+        s.epoch = 1;
+    }
+    const uint32_t ep = s.epoch;
+    auto &L = s.L;
+    auto &ex = s.expanded;
+    L.clear();
+    ex.clear();
+    const float *xp = B.row(p);
+    auto make = [&](int32_t u) { return Key{B.capped(ti, p, u), l2sq(xp, B.row(u), B.d), u}; };
+    int32_t entry = B.entry;
+    L.push_back(make(entry));
+    ex.push_back(0);
+    s.seen[entry] = ep;
+    size_t hint = 0;
+    for (;;) {
+        while (hint < L.size() && ex[hint]) hint++;
+        if (hint >= L.size()) break;
+        size_t pi = hint;
+        ex[pi] = 1;
+        int32_t v = L[pi].id;
+        s.visited.push_back(v);
+        const int32_t *nb = &B.adj[(size_t)v * B.R];
+        int dv = B.deg[v];
+        size_t min_ins = L.size();
+        for (int j = 0; j < dv; j++) {
+            int32_t u = nb[j];
+            if (s.seen[u] == ep) continue;
+            s.seen[u] = ep;
+            Key c = make(u);
+            if ((int)L.size() >= B.lb && !key_lt(c, L.back())) continue;
+            size_t pos = std::upper_bound(L.begin(), L.end(), c, key_lt) - L.begin();
+            L.insert(L.begin() + pos, c);
+            ex.insert(ex.begin() + pos, 0);
+            if ((int)L.size() > B.lb) {
+                L.pop_back();
+                ex.pop_back();
+            }
+            if (pos < min_ins) min_ins = pos;
+        }
+        hint = std::min(min_ins, pi + 1);
+    }
+}
+
+// JointRobustPrune(G, p, V, R, alpha, T) with the Appendix D.3 notes.
+int prune(const Builder &B, Scratch &s, int64_t p, const int32_t *V, int nv, int32_t *out)
+{
+    const float *xp = B.row(p);
+    auto &pd2 = s.pd2;
+    auto &pf = s.pf;
+    auto &order = s.order;
+    auto &flag = s.chosen_flag;
+    auto &bucket = s.bucket;
+    auto &chosen = s.chosen;
+    pd2.resize(nv);
+    pf.resize(nv);
+    order.resize(nv);
+    flag.assign(nv, 0);
+    chosen.clear();
+    for (int j = 0; j < nv; j++) pd2[j] = l2sq(xp, B.row(V[j]), B.d);
+    for (int ti = 0; ti < B.nT; ti++) {
+        for (int j = 0; j < nv; j++) {
+            pf[j] = B.capped(ti, p, V[j]);
+            order[j] = j;
+        }
+        std::sort(order.begin(), order.end(), [&](int a, int b) {
+            if (pf[a] != pf[b]) return pf[a] < pf[b];
+            if (pd2[a] != pd2[b]) return pd2[a] < pd2[b];
+            return V[a] < V[b];
+        });
+        bucket.clear();
+        for (int oi = 0; oi < nv; oi++) {
+            int j = order[oi];
+            bool keep = true;
+            if (!flag[j]) {
+                const float *xv = B.row(V[j]);
+                for (int bj : bucket) {
+                    if (!(B.alpha2 * l2sq(B.row(V[bj]), xv, B.d) > pd2[j])) {
+                        keep = false;
+                        break;
+                    }
+                }
+            }
+            if (keep) bucket.push_back(j);
+            if ((int)bucket.size() >= B.cap) break;
+        }
+        for (int j : bucket) {
+            if (!flag[j]) {
+                flag[j] = 1;
+                chosen.push_back(V[j]);
+            }
+        }
+    }
+    int m = std::min<int>((int)chosen.size(), B.R);
+    std::copy(chosen.begin(), chosen.begin() + m, out);
+    return m;
+}
+
+}  // namespace
+
+int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
+                std::vector<int32_t> &adj, int32_t &entry)
+{
+    Builder B;
+    B.X = X;
+    B.n = n;
+    B.d = d;
+    B.A = A;
+    B.R = cfg.R;
+    B.lb = cfg.L_build > 0 ? cfg.L_build : 2 * cfg.R;
+    B.nT = (int)cfg.kinds.size();
+    B.cap = (9 * B.R + 10 * B.nT - 1) / (10 * B.nT);
+    B.alpha2 = cfg.alpha * cfg.alpha;
+    B.kinds = cfg.kinds;
+    int nth = cfg.n_threads > 0 ? cfg.n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+
+    // entry vertex: nearest to the FP64 centroid, smaller id on ties
+    std::vector<double> cen(d, 0.0);
+    for (int64_t i = 0; i < n; i++)
+        for (int j = 0; j < d; j++) cen[j] += X[(size_t)i * d + j];
+    for (int j = 0; j < d; j++) cen[j] /= (double)n;
+    {
+        std::vector<double> best(nth, std::numeric_limits<double>::infinity());
+        std::vector<int64_t> bid(nth, -1);
+        int64_t chunk = (n + nth - 1) / nth;
+        parallel_for(nth, nth, [&](int64_t t, int) {
+            for (int64_t i = t * chunk; i < std::min(n, (t + 1) * chunk); i++) {
+                double acc = 0.0;
+                for (int j = 0; j < d; j++) {
+                    double u = (double)X[(size_t)i * d + j] - cen[j];
+                    acc += u * u;
+                }
+                if (acc < best[t]) {
+                    best[t] = acc;
+                    bid[t] = i;
+                }
+            }
+        });
+        int64_t e = 0;
+        double be = std::numeric_limits<double>::infinity();
+        for (int t = 0; t < nth; t++)
+            if (bid[t] >= 0 && best[t] < be) {
+                be = best[t];
+                e = bid[t];
+            }
+        entry = (int32_t)e;
+        B.entry = entry;
+    }
+
+    // per-point thresholds: nearest-rank quantile of dist_A over 500 samples
+    B.thr.assign((size_t)n * B.nT, 0.f);
+    parallel_for(n, nth, [&](int64_t p, int) {
+        float vals[500];
+        for (int ti = 0; ti < B.nT; ti++) {
+            float q = cfg.quantiles[ti];
+            float t;
+            if (q >= 1.f) t = std::numeric_limits<float>::infinity();
+            else if (q <= 0.f || n < 2) t = 0.f;
+            else {
+                uint64_t ctr = mix64(cfg.seed * 0x100000001B3ull + (uint64_t)p * 8 + ti);
+                for (int s = 0; s < 500; s++) {
+                    int64_t v;
+                    do {
+                        ctr = mix64(ctr);
+                        v = (int64_t)(ctr % (uint64_t)n);
+                    } while (v == p);
+                    vals[s] = B.dist_a(B.kinds[ti], p, v);
+                }
+                int r = (int)std::ceil((double)q * 500.0);
+                r = std::max(1, std::min(500, r));
+                std::nth_element(vals, vals + (r - 1), vals + 500);
+                t = vals[r - 1];
+            }
+            B.thr[(size_t)p * B.nT + ti] = t;
+        }
+    }, 256);
+
+    // insertion order: entry first, then a seeded permutation
+    std::vector<int32_t> order;
+    order.reserve(n);
+    order.push_back(entry);
+    for (int64_t i = 0; i < n; i++)
+        if (i != entry) order.push_back((int32_t)i);
+    {
+        uint64_t st = mix64(cfg.seed ^ 0xC0FFEEull);
+        for (int64_t i = n - 1; i > 1; i--) {
+            st = mix64(st);
+            int64_t j = 1 + (int64_t)(st % (uint64_t)i);
+            std::swap(order[i], order[j]);
+        }
+    }
+
+    B.adj.assign((size_t)n * B.R, -1);
+    B.deg.assign(n, 0);
+    std::vector<Scratch> scr(nth);
+    for (auto &s : scr) s.seen.assign(n, 0);
+    int64_t max_batch = cfg.max_batch > 0 ? cfg.max_batch : std::max<int64_t>(64, n / 50);
+    std::vector<std::vector<int32_t>> newrow;
+    int64_t pos = 1;  // order[0] = entry, inserted with no out-edges
+    int64_t bs = 1;
+    std::vector<std::pair<int32_t, int32_t>> rev;
+    while (pos < n) {
+        int64_t be = std::min<int64_t>(n, pos + bs);
+        int64_t nb = be - pos;
+        newrow.assign(nb, {});
+        // phase 1: searches against the frozen graph and the new vertex's own prune
+        parallel_for(nb, nth, [&](int64_t bi, int t) {
+            Scratch &s = scr[t];
+            int32_t p = order[pos + bi];
+            s.visited.clear();
+            for (int ti = 0; ti < B.nT; ti++) greedy_build_search(B, s, p, ti);
+            // union of the expanded sets without p and without repeats
+            std::sort(s.visited.begin(), s.visited.end());
+            s.visited.erase(std::unique(s.visited.begin(), s.visited.end()), s.visited.end());
+            s.visited.erase(std::remove(s.visited.begin(), s.visited.end(), p), s.visited.end());
+            int32_t outbuf[kMaxR];
+            int m = prune(B, s, p, s.visited.data(), (int)s.visited.size(), outbuf);
+            newrow[bi].assign(outbuf, outbuf + m);
+        });
+        for (int64_t bi = 0; bi < nb; bi++) {
+            int32_t p = order[pos + bi];
+            auto &r = newrow[bi];
+            std::copy(r.begin(), r.end(), &B.adj[(size_t)p * B.R]);
+            B.deg[p] = (int32_t)r.size();
+        }
+        // phase 2: reverse edges grouped by target vertex
+        rev.clear();
+        for (int64_t bi = 0; bi < nb; bi++)
+            for (int32_t v : newrow[bi]) rev.emplace_back(v, order[pos + bi]);
+        std::sort(rev.begin(), rev.end());
+        std::vector<int64_t> starts;
+        for (size_t i = 0; i < rev.size(); i++)
+            if (i == 0 || rev[i].first != rev[i - 1].first) starts.push_back((int64_t)i);
+        starts.push_back((int64_t)rev.size());
+        parallel_for((int64_t)starts.size() - 1, nth, [&](int64_t gi, int t) {
+            Scratch &s = scr[t];
+            int32_t v = rev[starts[gi]].first;
+            int32_t *rv = &B.adj[(size_t)v * B.R];
+            std::vector<int32_t> merged(rv, rv + B.deg[v]);
+            for (int64_t i = starts[gi]; i < starts[gi + 1]; i++) {
+                int32_t p = rev[i].second;
+                if (std::find(merged.begin(), merged.end(), p) == merged.end()) merged.push_back(p);
+            }
+            if ((int)merged.size() <= B.R) {
+                std::copy(merged.begin(), merged.end(), rv);
+                B.deg[v] = (int32_t)merged.size();
+            } else {
+                int32_t outbuf[kMaxR];
+                int m = prune(B, s, v, merged.data(), (int)merged.size(), outbuf);
+                std::copy(outbuf, outbuf + m, rv);
+                for (int j = m; j < B.R; j++) rv[j] = -1;
+                B.deg[v] = m;
+            }
+        }, 16);
+        pos = be;
+        bs = std::min<int64_t>(bs * 2, max_batch);
+    }
+    adj.swap(B.adj);
+    return 0;
+}
+
+}  // namespace jag

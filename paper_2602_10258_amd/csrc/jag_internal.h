@@ -1,0 +1,131 @@
+// Internal declarations shared by the host and device parts of libjag.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "jag.h"
+
+namespace jag {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+
+// ---------------------------------------------------------------- filters
+enum : int32_t { F_LABEL = 0, F_RANGE = 1, F_SUBSET = 2, F_BOOLEAN = 3 };
+
+constexpr int kMaxFilterLits = 16;
+constexpr int kMaxClauses = 8;
+constexpr uint32_t kUnsat = 0xFFFFFFFFu;  // dist_F when no attribute can satisfy the filter
+
+// Device filter record, JAG_FILTER_RECORD_BYTES bytes, read with scalar loads.
+struct alignas(16) FilterRecord {
+    int32_t type;                   // F_*
+    int32_t a;                      // LABEL: label; RANGE: lo
+    int32_t b;                      // RANGE: hi
+    int32_t nlit;                   // SUBSET: labels; BOOLEAN: distinct literals
+    int32_t ncl;                    // BOOLEAN: satisfiable clauses (0 = never satisfiable)
+    uint32_t negmask;               // BOOLEAN: bit i set = literal i asks for absence
+    float sel_feature;              // log2(selectivity estimate) / 16
+    float selectivity;              // estimate in [0, 1]
+    uint16_t lits[kMaxFilterLits];  // labels of the literals / required labels
+    uint16_t clmask[kMaxClauses];   // BOOLEAN: literals of each clause (bitmask)
+    int32_t pad[12];
+};
+static_assert(sizeof(FilterRecord) == JAG_FILTER_RECORD_BYTES, "record size");
+
+// ---------------------------------------------------------------- index
+constexpr int kMaxDim = 512;
+constexpr int kMaxR = 64;
+constexpr int kMaxLabelsPerItem = 16;
+constexpr int kPredParams = 5313;
+
+struct Predictor {
+    bool present = false;
+    std::vector<float> params;  // FP32 as given
+    uint16_t *d_bf16 = nullptr; // device BF16 copy (5313 padded to 5376)
+    int32_t nladder = 0;
+    int32_t ladder[JAG_LADDER_MAX] = {0};
+    float rho = 0.f;
+};
+
+struct Index {
+    int64_t n = 0;
+    int32_t d = 0, R = 0, entry = 0, store = JAG_STORE_F32;
+    bool keep_f32 = false;
+    bool has_scalar = false, has_labels = false;
+    int32_t W = 0;      // label row width on the device (uint16 slots, 0xFFFF padded)
+    int32_t vocab = 0;
+    // host copies (kept for persistence, selectivity estimates and export)
+    std::vector<float> X;
+    std::vector<int32_t> adj;
+    std::vector<int32_t> scalar;
+    std::vector<int64_t> loff;
+    std::vector<int32_t> lab;
+    std::vector<int32_t> scalar_sorted;
+    std::vector<int64_t> label_count;
+    // device memory
+    int device = 0;
+    int32_t *d_adj = nullptr;
+    unsigned char *d_vec = nullptr;  // search store rows, vec_stride bytes each
+    int32_t vec_stride = 0;
+    unsigned char *d_f32 = nullptr;  // FP32 rows (== d_vec for an FP32 store), f32_stride bytes
+    int32_t f32_stride = 0;
+    bool f32_owned = false;
+    int32_t *d_scalar = nullptr;
+    uint16_t *d_lab = nullptr;
+    int64_t device_bytes = 0;
+    Predictor pred;
+};
+
+// Row stride of a store: rows are padded to a multiple of 64 bytes; an FP8
+// row keeps its FP32 scale in its last 4 bytes.
+int32_t store_row_bytes(int32_t store, int32_t d);
+
+// ---------------------------------------------------------------- builder
+struct BuildConfig {
+    int32_t R = 32, L_build = 64;
+    float alpha = 1.2f;
+    std::vector<int32_t> kinds;
+    std::vector<float> quantiles;
+    uint64_t seed = 0;
+    int32_t n_threads = 0;
+    int32_t max_batch = 0;
+};
+
+struct AttrView {
+    int64_t n = 0;
+    const int32_t *scalar = nullptr;
+    const int64_t *loff = nullptr;
+    const int32_t *lab = nullptr;
+};
+
+// Threshold-JAG construction on host threads; fills adj[n*R] (-1 padded).
+int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
+                std::vector<int32_t> &adj, int32_t &entry);
+
+// ---------------------------------------------------------------- device side
+// All of these run on the calling thread's current device and report errors
+// through set_error, returning a jag_status.
+jag_status upload_index(Index &ix);
+void free_device(Index &ix);
+jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
+                         const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
+                         void *stream);
+jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
+                        int32_t *ids, float *dists, int32_t *count, void *stream);
+jag_status upload_predictor(Index &ix);
+jag_status download_store(const Index &ix, void *rows_out, float *scales_out);
+jag_status train_predictor(const float *features, const float *targets, int64_t m,
+                           float *params_inout, int32_t epochs, int32_t batch, float lr,
+                           uint64_t seed, float *loss_out, void *stream);
+jag_status predictor_grad(const float *features, const float *targets, int64_t m,
+                          const float *params, float *loss_out, float *grad_out, void *stream);
+
+// Host-side filter encoding with the index's selectivity estimate.
+jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                          int64_t pool_len, FilterRecord *out);
+
+}  // namespace jag

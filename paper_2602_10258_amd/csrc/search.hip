@@ -1,0 +1,1094 @@
+// Batched filtered greedy search on gfx950 (paper Algorithms 1 and 2 with
+// the comparator D_F of Section 3.2), one 64-lane wavefront per query.
+//
+// Per query the wavefront keeps, in LDS:
+//   key[Lcap] : (dist_F << 32) | float bits of the squared distance; equal
+//               keys are ordered by vertex id, so the order is total
+//   idf[Lcap] : vertex id, bit 31 = expanded
+//   hash[H]   : ids already discovered.  It may forget ids (a full probe
+//               window overwrites its first slot) but never reports an id it
+//               was not given.  Forgetting is harmless: the candidate list is
+//               always the l_s best of every vertex discovered so far, so a
+//               vertex that fell out of it cannot re-enter, and one that is
+//               still in it is recognised by its identical (key, id) when it
+//               is merged again.
+// One hop: take the first unexpanded entry p, read p's adjacency row (one
+// coalesced 256-byte load), drop ids already discovered, evaluate dist_F of
+// the rest from their attributes (exact integers), drop those whose dist_F
+// exceeds that of the worst entry of a full list (they can never enter: the
+// order is lexicographic), gather the surviving vectors four lanes per row
+// and merge the new keys into the sorted list, cutting it to l_s.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "jag_internal.h"
+
+namespace jag {
+
+namespace {
+
+constexpr uint32_t kExpanded = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7FFFFFFFu;
+
+struct SearchArgs {
+    const int32_t *adj;
+    const unsigned char *vec;
+    const unsigned char *f32;
+    const int32_t *scalar;
+    const uint16_t *lab;
+    const float *Q;
+    const FilterRecord *rec;
+    int32_t *ids;
+    float *dists;
+    int32_t *count;
+    int32_t *stats;
+    float *features;
+    const uint16_t *pred;
+    int32_t vec_stride, f32_stride, W, d, R, entry;
+    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder;
+    float delta, rho;
+    int32_t ladder[JAG_LADDER_MAX];
+};
+
+__device__ __forceinline__ bool key_lt(uint64_t ka, uint32_t ia, uint64_t kb, uint32_t ib)
+{
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ---------------------------------------------------------------- dist_F
+// Section 3.1: label -> [label missing]; range -> distance to [lo, hi];
+// subset -> number of required labels missing; Boolean DNF -> fewest
+// literals to flip in the cheapest satisfiable clause.
+__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, int32_t u, const SearchArgs &a)
+{
+    if (f.type == F_RANGE) {
+        int64_t v = a.scalar[u];
+        if (v < f.a) return (uint32_t)((int64_t)f.a - v);
+        if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
+        return 0u;
+    }
+    uint32_t w[8];
+    const unsigned char *row = reinterpret_cast<const unsigned char *>(a.lab) + (int64_t)u * a.W * 2;
+    int nw = a.W >> 1;
+    if (nw == 1) {
+        w[0] = *reinterpret_cast<const uint32_t *>(row);
+    } else if (nw == 2) {
+        uint2 t = *reinterpret_cast<const uint2 *>(row);
+        w[0] = t.x;
+        w[1] = t.y;
+    } else {
+        uint4 t = *reinterpret_cast<const uint4 *>(row);
+        w[0] = t.x;
+        w[1] = t.y;
+        w[2] = t.z;
+        w[3] = t.w;
+        if (nw == 8) {
+            uint4 s = *reinterpret_cast<const uint4 *>(row + 16);
+            w[4] = s.x;
+            w[5] = s.y;
+            w[6] = s.z;
+            w[7] = s.w;
+        }
+    }
+    // static loop bounds keep the (uniform) record in scalar registers
+    uint32_t present = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxFilterLits; i++) {
+        if (i < f.nlit) {
+            uint32_t l = f.lits[i];
+            bool hit = false;
+#pragma unroll
+            for (int j = 0; j < 8; j++)
+                if (j < nw) hit |= ((w[j] & 0xFFFFu) == l) | ((w[j] >> 16) == l);
+            present |= (uint32_t)hit << i;
+        }
+    }
+    if (f.type == F_LABEL) return (present & 1u) ? 0u : 1u;
+    if (f.type == F_SUBSET) return (uint32_t)(f.nlit - __builtin_popcount(present));
+    uint32_t truth = present ^ f.negmask;
+    uint32_t best = kUnsat;
+#pragma unroll
+    for (int c = 0; c < kMaxClauses; c++) {
+        if (c < f.ncl) {
+            uint32_t cost = (uint32_t)__builtin_popcount((uint32_t)f.clmask[c] & ~truth);
+            best = cost < best ? cost : best;
+        }
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------- distances
+template <int STORE>
+struct StoreTraits;
+template <>
+struct StoreTraits<JAG_STORE_F32> {
+    static constexpr int EPC = 4;
+};
+template <>
+struct StoreTraits<JAG_STORE_BF16> {
+    static constexpr int EPC = 8;
+};
+template <>
+struct StoreTraits<JAG_STORE_FP8_E4M3> {
+    static constexpr int EPC = 16;
+};
+
+// The query in registers: lane `sub` of a G-lane group holds the elements
+// of the 16-byte chunks j*G + sub of a row (zero beyond d).
+template <int STORE, int G, int CH>
+struct QueryRegs {
+    float v[CH][StoreTraits<STORE>::EPC];
+    __device__ __forceinline__ void load(const float *q, int d, int sub)
+    {
+        constexpr int EPC = StoreTraits<STORE>::EPC;
+#pragma unroll
+        for (int j = 0; j < CH; j++)
+#pragma unroll
+            for (int e = 0; e < EPC; e++) {
+                int idx = (j * G + sub) * EPC + e;
+                v[j][e] = idx < d ? q[idx] : 0.f;
+            }
+    }
+};
+
+__device__ __forceinline__ float acc_sq(float acc, float qv, float x)
+{
+    float t = qv - x;
+    return __builtin_fmaf(t, t, acc);
+}
+
+// Partial squared distance of one row held by a G-lane group; the partial
+// sums of the group are then added in a fixed butterfly order.
+template <int STORE, int G, int CH>
+__device__ __forceinline__ float row_dist(const unsigned char *row, const QueryRegs<STORE, G, CH> &q,
+                                          int sub)
+{
+    uint4 c[CH];
+#pragma unroll
+    for (int j = 0; j < CH; j++)
+        c[j] = *reinterpret_cast<const uint4 *>(row + (j * G + sub) * 16);
+    float acc = 0.f;
+    if constexpr (STORE == JAG_STORE_F32) {
+#pragma unroll
+        for (int j = 0; j < CH; j++) {
+            acc = acc_sq(acc, q.v[j][0], __uint_as_float(c[j].x));
+            acc = acc_sq(acc, q.v[j][1], __uint_as_float(c[j].y));
+            acc = acc_sq(acc, q.v[j][2], __uint_as_float(c[j].z));
+            acc = acc_sq(acc, q.v[j][3], __uint_as_float(c[j].w));
+        }
+    } else if constexpr (STORE == JAG_STORE_BF16) {
+#pragma unroll
+        for (int j = 0; j < CH; j++) {
+            uint32_t w[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                acc = acc_sq(acc, q.v[j][2 * t], __uint_as_float(w[t] << 16));
+                acc = acc_sq(acc, q.v[j][2 * t + 1], __uint_as_float(w[t] & 0xFFFF0000u));
+            }
+        }
+    } else {
+        // the row's FP32 scale sits in the last 4 bytes: chunk CH-1 of lane G-1
+        uint32_t sbits = c[CH - 1].w;
+        float s = __uint_as_float(__shfl(sbits, (threadIdx.x & ~(G - 1)) | (G - 1), 64));
+#pragma unroll
+        for (int j = 0; j < CH; j++) {
+            uint32_t w[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                if (j == CH - 1 && t == 3 && sub == G - 1) continue;  // the scale, not codes
+                auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[t], false);
+                auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[t], true);
+                acc = acc_sq(acc, q.v[j][4 * t + 0], s * lo[0]);
+                acc = acc_sq(acc, q.v[j][4 * t + 1], s * lo[1]);
+                acc = acc_sq(acc, q.v[j][4 * t + 2], s * hi[0]);
+                acc = acc_sq(acc, q.v[j][4 * t + 3], s * hi[1]);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) acc += __shfl_xor(acc, m, 64);
+    return acc;
+}
+
+// Squared distances of the m candidates cid[0..m) into cd2[], G lanes per row.
+template <int STORE, int G, int CH>
+__device__ __forceinline__ void eval_rows(const unsigned char *base, int stride, const int32_t *cid,
+                                          float *cd2, int m, const QueryRegs<STORE, G, CH> &q)
+{
+    const int lane = threadIdx.x;
+    const int sub = lane & (G - 1), grp = lane / G;
+    constexpr int P = 64 / G;
+    for (int r = 0; r < m; r += 2 * P) {
+        int c0 = r + grp, c1 = r + P + grp;
+        // rows past m re-read row cid[0] so every lane stays in bounds
+        int i0 = cid[c0 < m ? c0 : 0], i1 = cid[c1 < m ? c1 : 0];
+        float d0 = row_dist<STORE, G, CH>(base + (int64_t)i0 * stride, q, sub);
+        float d1 = 0.f;
+        if (r + P < m) d1 = row_dist<STORE, G, CH>(base + (int64_t)i1 * stride, q, sub);
+        if (sub == 0 && c0 < m) cd2[c0] = d0;
+        if (sub == 0 && c1 < m) cd2[c1] = d1;
+    }
+}
+
+// Generic FP32 row distance with a runtime chunk count (for reranking).
+__device__ __forceinline__ float row_dist_f32_rt(const unsigned char *row, const float *q, int d,
+                                                 int nch, int sub)
+{
+    float acc = 0.f;
+    for (int j = 0; j < nch; j++) {
+        int e0 = (j * 4 + sub) * 4;
+        float4 x = *reinterpret_cast<const float4 *>(row + (j * 4 + sub) * 16);
+        float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc = acc_sq(acc, e0 + e < d ? q[e0 + e] : 0.f, xs[e]);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    return acc;
+}
+
+// ---------------------------------------------------------------- LDS list
+struct Lds {
+    uint64_t *key;
+    uint32_t *idf;
+    int32_t *hash;
+    int32_t *cid;
+    uint32_t *cdf;
+    float *cd2;
+    uint64_t *skey;
+    uint32_t *sid;
+    int32_t *spos;
+    float *feat;
+    float *h1;
+    uint64_t *exkey;
+};
+
+__device__ __forceinline__ Lds carve(unsigned char *smem, int Lcap, int H)
+{
+    Lds s;
+    s.key = reinterpret_cast<uint64_t *>(smem);
+    s.skey = s.key + Lcap;
+    s.exkey = s.skey + 64;
+    s.idf = reinterpret_cast<uint32_t *>(s.exkey + 4);
+    s.hash = reinterpret_cast<int32_t *>(s.idf + Lcap);
+    s.cid = s.hash + H;
+    s.cdf = reinterpret_cast<uint32_t *>(s.cid + 64);
+    s.cd2 = reinterpret_cast<float *>(s.cdf + 64);
+    s.sid = reinterpret_cast<uint32_t *>(s.cd2 + 64);
+    s.spos = reinterpret_cast<int32_t *>(s.sid + 64);
+    s.feat = reinterpret_cast<float *>(s.spos + 64);
+    s.h1 = s.feat + 16;
+    return s;
+}
+
+__host__ __device__ constexpr size_t lds_bytes(int Lcap, int H)
+{
+    return (size_t)Lcap * 8 + 64 * 8 + 4 * 8 + (size_t)Lcap * 4 + (size_t)H * 4 + 64 * 4 * 6 + 16 * 4 +
+           64 * 4;
+}
+
+// Insert id u into the lossy hash; true if u was not found (newly seen).
+__device__ __forceinline__ bool hash_insert(int32_t *hash, int mask, int32_t u)
+{
+    uint32_t h = (uint32_t)u * 0x9E3779B1u;
+    h ^= h >> 15;
+    for (int t = 0; t < 4; t++) {
+        int s = (int)((h + t) & (uint32_t)mask);
+        int32_t v = hash[s];
+        if (v == u) return false;
+        if (v == -1) {
+            hash[s] = u;
+            return true;
+        }
+    }
+    hash[h & (uint32_t)mask] = u;
+    return true;
+}
+
+// First entry at or after `from` whose expanded bit is clear, or cnt.
+__device__ __forceinline__ int first_unexpanded(const Lds &s, int from, int cnt)
+{
+    const int lane = threadIdx.x;
+    for (int j0 = from; j0 < cnt; j0 += 64) {
+        int j = j0 + lane;
+        bool un = j < cnt && !(s.idf[j] & kExpanded);
+        uint64_t b = ballot64(un);
+        if (b) return j0 + __builtin_ctzll(b);
+    }
+    return cnt;
+}
+
+// Merge candidates (lane c < m holds cid/cdf/cd2 slot c) into the sorted
+// list of cnt entries, keeping at most ls.  Returns the new size; *minpos is
+// the list position of the best inserted candidate (ls if none).
+__device__ int merge_candidates(const Lds &s, int m, int cnt, int ls, int *minpos)
+{
+    const int lane = threadIdx.x;
+    bool have = lane < m;
+    uint64_t ck = 0;
+    uint32_t ci = 0;
+    if (have) {
+        ck = ((uint64_t)s.cdf[lane] << 32) | __float_as_uint(s.cd2[lane]);
+        ci = (uint32_t)s.cid[lane];
+    }
+    if (have && cnt == ls) {
+        uint64_t wk = s.key[cnt - 1];
+        uint32_t wi = s.idf[cnt - 1] & kIdMask;
+        if (!key_lt(ck, ci, wk, wi)) have = false;
+    }
+    int pos = 0;
+    if (have) {
+        int lo = 0, hi = cnt;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (key_lt(s.key[mid], s.idf[mid] & kIdMask, ck, ci)) lo = mid + 1;
+            else hi = mid;
+        }
+        pos = lo;
+        if (pos < cnt && s.key[pos] == ck && (s.idf[pos] & kIdMask) == ci) have = false;
+    }
+    uint64_t vm = ballot64(have);
+    int mv = __popcll(vm);
+    if (mv == 0) {
+        *minpos = ls;
+        return cnt;
+    }
+    // rank among the surviving candidates (written compacted to skey/sid first)
+    int slot = lanes_below(vm);
+    if (have) {
+        s.skey[slot] = ck;
+        s.sid[slot] = ci;
+    }
+    __syncthreads();
+    int rank = 0;
+    if (have)
+        for (int j = 0; j < mv; j++) rank += key_lt(s.skey[j], s.sid[j], ck, ci) ? 1 : 0;
+    __syncthreads();
+    if (have) {
+        s.skey[rank] = ck;
+        s.sid[rank] = ci;
+        s.spos[rank] = pos;
+    }
+    __syncthreads();
+    int mp = s.spos[0];
+    int newcnt = cnt + mv < ls ? cnt + mv : ls;
+    // shift list entries right by the number of candidates before them,
+    // chunk by chunk from the end so no unread entry is overwritten
+    int top = ((cnt - 1) >> 6) << 6;
+    for (int j0 = top; j0 >= (mp & ~63); j0 -= 64) {
+        int j = j0 + lane;
+        uint64_t kj = 0;
+        uint32_t ij = 0;
+        bool mv_ = j < cnt && j >= mp;
+        if (mv_) {
+            kj = s.key[j];
+            ij = s.idf[j];
+        }
+        int sh = 0;
+        if (mv_) {
+            int lo = 0, hi = mv;
+            uint32_t id = ij & kIdMask;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (key_lt(s.skey[mid], s.sid[mid], kj, id)) lo = mid + 1;
+                else hi = mid;
+            }
+            sh = lo;
+        }
+        __syncthreads();
+        if (mv_ && j + sh < ls) {
+            s.key[j + sh] = kj;
+            s.idf[j + sh] = ij;
+        }
+        __syncthreads();
+    }
+    if (have && pos + rank < ls) {
+        s.key[pos + rank] = ck;
+        s.idf[pos + rank] = ci;
+    }
+    __syncthreads();
+    *minpos = mp;
+    return newcnt;
+}
+
+__device__ __forceinline__ float squash(uint32_t df)
+{
+    float x = (float)df;
+    return x / (x + 1.0f);
+}
+
+__device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Beam predictor: 16 -> 64 -> 64 -> 1, ReLU, BF16 weights, FP32 sums.
+// Lane j computes hidden unit j; the output is a butterfly sum over lanes.
+__device__ float predict(const Lds &s, const uint16_t *P)
+{
+    const int lane = threadIdx.x;
+    const uint16_t *W1 = P, *b1 = P + 1024, *W2 = P + 1088, *b2 = P + 5184, *w3 = P + 5248,
+                   *b3 = P + 5312;
+    float acc = bf16f(b1[lane]);
+#pragma unroll
+    for (int i = 0; i < 16; i++) acc = __builtin_fmaf(bf16f(W1[lane * 16 + i]), s.feat[i], acc);
+    s.h1[lane] = acc > 0.f ? acc : 0.f;
+    __syncthreads();
+    float acc2 = bf16f(b2[lane]);
+    for (int i = 0; i < 64; i++) acc2 = __builtin_fmaf(bf16f(W2[lane * 64 + i]), s.h1[i], acc2);
+    float h2 = acc2 > 0.f ? acc2 : 0.f;
+    float t = bf16f(w3[lane]) * h2;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+    __syncthreads();
+    return t + bf16f(b3[0]);
+}
+
+template <int STORE, int G, int CH>
+__global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const int H = a.Hmask + 1;
+    Lds s = carve(smem, a.Lcap, H);
+    const FilterRecord f = a.rec[q];
+    const float *qv = a.Q + q * a.d;
+    QueryRegs<STORE, G, CH> qr;
+    qr.load(qv, a.d, lane & (G - 1));
+    for (int i = lane; i < H; i += 64) s.hash[i] = -1;
+
+    // L <- {s}
+    if (lane == 0) {
+        s.cid[0] = a.entry;
+        s.cdf[0] = dist_f(f, a.entry, a);
+    }
+    __syncthreads();
+    eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, 1, qr);
+    __syncthreads();
+    if (lane == 0) {
+        s.key[0] = ((uint64_t)s.cdf[0] << 32) | __float_as_uint(s.cd2[0]);
+        s.idf[0] = (uint32_t)a.entry;
+        hash_insert(s.hash, a.Hmask, a.entry);
+    }
+    __syncthreads();
+    int cnt = 1, hint = 0, hops = 0, ndist = 1, nattr = 1;
+    // learned and trace modes keep every discovered vertex during the first
+    // four expansions (Lcap >= 1 + 4R), so the features do not depend on a beam
+    int ls = a.mode == 0 ? a.L : a.Lcap;
+    int hopcap = a.max_hops > 0 ? a.max_hops : INT_MAX;
+    int lhat = a.mode == 1 ? 0 : a.L;
+    bool predicted = a.mode == 0;
+    for (;;) {
+        hint = first_unexpanded(s, hint, cnt);
+        if (hint >= cnt || hops >= hopcap) break;
+        const int p = (int)(s.idf[hint] & kIdMask);
+        __syncthreads();
+        if (lane == 0) {
+            s.idf[hint] |= kExpanded;
+            if (hops < 4) s.exkey[hops] = s.key[hint];
+        }
+        hops++;
+        int32_t u = lane < a.R ? a.adj[(int64_t)p * a.R + lane] : -1;
+        bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
+        uint32_t df = fresh ? dist_f(f, u, a) : 0u;
+        nattr += __popcll(ballot64(fresh));
+        if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
+        uint64_t bm = ballot64(fresh);
+        int m = __popcll(bm);
+        if (fresh) {
+            int slot = lanes_below(bm);
+            s.cid[slot] = u;
+            s.cdf[slot] = df;
+        }
+        __syncthreads();
+        int minpos = INT_MAX;
+        if (m > 0) {
+            eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
+            __syncthreads();
+            ndist += m;
+            cnt = merge_candidates(s, m, cnt, ls, &minpos);
+        }
+        hint = minpos < hint + 1 ? minpos : hint + 1;
+        if (!predicted && hops == 4) {
+            predicted = true;
+            // predictor features after the fourth expansion
+            int valid = 0;
+            for (int j0 = 0; j0 < cnt; j0 += 64) {
+                int j = j0 + lane;
+                valid += __popcll(ballot64(j < cnt && (s.key[j] >> 32) == 0));
+            }
+            if (lane == 0) {
+                for (int i = 0; i < 16; i++) s.feat[i] = 0.f;
+                s.feat[f.type] = 1.f;
+                s.feat[4] = f.sel_feature;
+                float b = __uint_as_float((uint32_t)s.exkey[0]);
+                b = b > 1e-30f ? b : 1e-30f;
+                for (int j = 1; j < 4; j++) s.feat[4 + j] = __uint_as_float((uint32_t)s.exkey[j]) / b;
+                s.feat[8] = __uint_as_float((uint32_t)s.key[0]) / b;
+                for (int j = 0; j < 4; j++) s.feat[9 + j] = squash((uint32_t)(s.exkey[j] >> 32));
+                s.feat[13] = squash((uint32_t)(s.key[0] >> 32));
+                s.feat[14] = (float)valid / (float)cnt;
+                s.feat[15] = 1.f;
+            }
+            __syncthreads();
+            if (a.mode == 2) {
+                if (lane < 16) a.features[q * 16 + lane] = s.feat[lane];
+                if (cnt > a.L) cnt = a.L;
+                ls = a.L;
+            } else {
+                float y = predict(s, a.pred);
+                float z = y + a.delta;
+                int idx;
+                if (!(z == z)) idx = a.nladder - 1;
+                else {
+                    float c = ceilf(z);
+                    idx = c < 0.f ? 0 : (c > (float)(a.nladder - 1) ? a.nladder - 1 : (int)c);
+                }
+#pragma unroll
+                for (int i = 0; i < JAG_LADDER_MAX; i++)
+                    if (i == idx) lhat = a.ladder[i];
+                float capf = ceilf(a.rho * (float)lhat);
+                int cap = capf >= 2147483647.0f ? INT_MAX : (int)capf;
+                cap = cap < 4 ? 4 : cap;
+                hopcap = cap < hopcap ? cap : hopcap;
+                if (cnt > lhat) cnt = lhat;
+                ls = lhat;
+            }
+        }
+    }
+    if (a.mode == 2 && !predicted && lane < 16)  // fewer than four expansions: no features
+        a.features[q * 16 + lane] = lane == 15 ? -1.f : 0.f;
+    // ---- output: top-k valid entries, optionally rescored in FP32
+    int outn = cnt;
+    if (a.rerank > 0) {
+        int rk = a.rerank * a.k;
+        rk = rk < cnt ? rk : cnt;
+        if (lane < rk) {
+            s.cid[lane] = (int32_t)(s.idf[lane] & kIdMask);
+            s.cdf[lane] = (uint32_t)(s.key[lane] >> 32);
+        }
+        __syncthreads();
+        const int sub = lane & 3, grp = lane >> 2;
+        const int nch = a.f32_stride >> 6;
+        for (int r = 0; r < rk; r += 16) {
+            int c = r + grp;
+            int id = s.cid[c < rk ? c : 0];
+            float dd = row_dist_f32_rt(a.f32 + (int64_t)id * a.f32_stride, qv, a.d, nch, sub);
+            if (sub == 0 && c < rk) s.cd2[c] = dd;
+        }
+        __syncthreads();
+        uint64_t ck = 0;
+        uint32_t ci = 0;
+        int rank = 0;
+        if (lane < rk) {
+            ck = ((uint64_t)s.cdf[lane] << 32) | __float_as_uint(s.cd2[lane]);
+            ci = (uint32_t)s.cid[lane];
+            for (int j = 0; j < rk; j++) {
+                uint64_t kj = ((uint64_t)s.cdf[j] << 32) | __float_as_uint(s.cd2[j]);
+                rank += key_lt(kj, (uint32_t)s.cid[j], ck, ci) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (lane < rk) {
+            s.key[rank] = ck;
+            s.idf[rank] = ci;
+        }
+        __syncthreads();
+        outn = rk;
+    }
+    bool ok = lane < a.k && lane < outn && (s.key[lane < outn ? lane : 0] >> 32) == 0;
+    if (lane < a.k) {
+        a.ids[q * a.k + lane] = ok ? (int32_t)(s.idf[lane] & kIdMask) : -1;
+        a.dists[q * a.k + lane] = ok ? __uint_as_float((uint32_t)s.key[lane]) : __builtin_inff();
+    }
+    int cntv = __popcll(ballot64(ok));
+    if (lane == 0) {
+        a.count[q] = cntv;
+        if (a.stats) {
+            a.stats[q * 4 + 0] = hops;
+            a.stats[q * 4 + 1] = ndist;
+            a.stats[q * 4 + 2] = nattr;
+            a.stats[q * 4 + 3] = lhat;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- exact k-NN
+// Pre-Filtering: every item is tested against the filter; valid items are
+// scored from the FP32 rows and merged into a k-entry list.
+template <int G, int CH>
+__global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    Lds s = carve(smem, a.Lcap, 1);
+    const FilterRecord f = a.rec[q];
+    QueryRegs<JAG_STORE_F32, G, CH> qr;
+    qr.load(a.Q + q * a.d, a.d, lane & (G - 1));
+    int cnt = 0;
+    for (int64_t i0 = 0; i0 < n; i0 += 64) {
+        int64_t i = i0 + lane;
+        bool ok = i < n;
+        uint32_t df = ok ? dist_f(f, (int32_t)i, a) : 1u;
+        ok = ok && df == 0;
+        uint64_t bm = ballot64(ok);
+        int m = __popcll(bm);
+        if (m == 0) continue;
+        if (ok) {
+            int slot = lanes_below(bm);
+            s.cid[slot] = (int32_t)i;
+            s.cdf[slot] = 0u;
+        }
+        __syncthreads();
+        eval_rows<JAG_STORE_F32, G, CH>(a.f32, a.f32_stride, s.cid, s.cd2, m, qr);
+        __syncthreads();
+        int mp;
+        cnt = merge_candidates(s, m, cnt, a.k, &mp);
+    }
+    bool ok = lane < cnt && lane < a.k;
+    if (lane < a.k) {
+        a.ids[q * a.k + lane] = ok ? (int32_t)(s.idf[lane] & kIdMask) : -1;
+        a.dists[q * a.k + lane] = ok ? __uint_as_float((uint32_t)s.key[lane]) : __builtin_inff();
+    }
+    if (lane == 0) a.count[q] = cnt < a.k ? cnt : a.k;
+}
+
+// ---------------------------------------------------------------- quantizers
+// FP32 -> BF16, round to nearest even (NaN stays NaN, quieted).
+__device__ __forceinline__ uint16_t to_bf16(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// FP32 -> OCP E4M3, round to nearest even, saturating at +-448.
+__device__ __forceinline__ uint8_t to_e4m3(float y)
+{
+    uint32_t u = __float_as_uint(y);
+    uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+    uint32_t a = u & 0x7FFFFFFFu;
+    if (a > 0x7F800000u) return 0x7F;
+    if (a >= 0x43E00000u) return (uint8_t)(sign | 0x7E);  // |y| >= 448
+    if (a < 0x3C800000u) {                                // |y| < 2^-6: subnormal step 2^-9
+        float m = __builtin_rintf(__uint_as_float(a) * 512.0f);
+        return (uint8_t)(sign | (uint8_t)m);               // m == 8 is the smallest normal
+    }
+    // keep 3 mantissa bits, round to nearest even on the 20 dropped bits
+    uint32_t r = a + 0x7FFFFu + ((a >> 20) & 1u);
+    uint32_t code = (r >> 20) - (120u << 3);
+    return (uint8_t)(sign | (uint8_t)code);
+}
+
+__global__ void quant_bf16_kernel(const float *X, int64_t n, int d, unsigned char *out, int stride)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = n * (int64_t)(stride / 2);
+    if (i >= tot) return;
+    int64_t r = i / (stride / 2);
+    int c = (int)(i % (stride / 2));
+    uint16_t v = c < d ? to_bf16(X[r * d + c]) : (uint16_t)0;
+    reinterpret_cast<uint16_t *>(out + r * stride)[c] = v;
+}
+
+// One 64-lane wave per row: max |x| by a butterfly, scale = max/448 (FP32
+// division), code_i = E4M3(x_i / scale); an all-zero row gets scale 1.
+__global__ __launch_bounds__(64) void quant_fp8_kernel(const float *X, int64_t n, int d,
+                                                       unsigned char *out, int stride)
+{
+    const int64_t r = blockIdx.x;
+    const int lane = threadIdx.x;
+    float mx = 0.f;
+    for (int c = lane; c < d; c += 64) mx = fmaxf(mx, fabsf(X[r * d + c]));
+    for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m, 64));
+    float s = mx > 0.f ? mx / 448.0f : 1.0f;
+    unsigned char *row = out + r * stride;
+    for (int c = lane; c < stride - 4; c += 64) row[c] = c < d ? to_e4m3(X[r * d + c] / s) : (uint8_t)0;
+    if (lane == 0) *reinterpret_cast<float *>(row + stride - 4) = s;
+}
+
+__global__ void copy_rows_kernel(const float *X, int64_t n, int d, unsigned char *out, int stride)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = n * (int64_t)(stride / 4);
+    if (i >= tot) return;
+    int64_t r = i / (stride / 4);
+    int c = (int)(i % (stride / 4));
+    reinterpret_cast<float *>(out + r * stride)[c] = c < d ? X[r * d + c] : 0.f;
+}
+
+__global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = to_bf16(x[i]);
+}
+
+// ---------------------------------------------------------------- host glue
+#define HIPCHK(expr)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));             \
+            return e_ == hipErrorOutOfMemory ? JAG_ENOMEM : JAG_EDEVICE;           \
+        }                                                                          \
+    } while (0)
+
+template <class T>
+jag_status dalloc(T **p, size_t bytes, int64_t &acct)
+{
+    HIPCHK(hipMalloc((void **)p, bytes));
+    acct += (int64_t)bytes;
+    return JAG_OK;
+}
+
+int pick_group(int stride) { return stride <= 512 ? 4 : 16; }
+
+using SearchFn = void (*)(SearchArgs);
+using ExactFn = void (*)(SearchArgs, int64_t);
+
+template <int STORE, int G>
+SearchFn search_for_ch(int ch)
+{
+    switch (ch) {
+    case 1: return search_kernel<STORE, G, 1>;
+    case 2: return search_kernel<STORE, G, 2>;
+    case 3: return search_kernel<STORE, G, 3>;
+    case 4: return search_kernel<STORE, G, 4>;
+    case 5: return search_kernel<STORE, G, 5>;
+    case 6: return search_kernel<STORE, G, 6>;
+    case 7: return search_kernel<STORE, G, 7>;
+    case 8: return search_kernel<STORE, G, 8>;
+    }
+    return nullptr;
+}
+
+SearchFn pick_search(int store, int stride)
+{
+    int G = pick_group(stride);
+    int ch = stride / (16 * G);
+    if (store == JAG_STORE_F32) return G == 4 ? search_for_ch<JAG_STORE_F32, 4>(ch) : search_for_ch<JAG_STORE_F32, 16>(ch);
+    if (store == JAG_STORE_BF16) return G == 4 ? search_for_ch<JAG_STORE_BF16, 4>(ch) : search_for_ch<JAG_STORE_BF16, 16>(ch);
+    return G == 4 ? search_for_ch<JAG_STORE_FP8_E4M3, 4>(ch) : search_for_ch<JAG_STORE_FP8_E4M3, 16>(ch);
+}
+
+template <int G>
+ExactFn exact_for_ch(int ch)
+{
+    switch (ch) {
+    case 1: return exact_kernel<G, 1>;
+    case 2: return exact_kernel<G, 2>;
+    case 3: return exact_kernel<G, 3>;
+    case 4: return exact_kernel<G, 4>;
+    case 5: return exact_kernel<G, 5>;
+    case 6: return exact_kernel<G, 6>;
+    case 7: return exact_kernel<G, 7>;
+    case 8: return exact_kernel<G, 8>;
+    }
+    return nullptr;
+}
+
+int hash_size_for(int Lcap)
+{
+    int h = 1024;
+    while (h < 16 * Lcap && h < 8192) h <<= 1;
+    return h;
+}
+
+}  // namespace
+
+jag_status upload_index(Index &ix)
+{
+    HIPCHK(hipGetDevice(&ix.device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, ix.device));
+    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0) {
+        set_error("device %d is %s; this library is built for gfx950 only", ix.device, prop.gcnArchName);
+        return JAG_EDEVICE;
+    }
+    const int64_t n = ix.n;
+    const int d = ix.d;
+    jag_status st;
+    if ((st = dalloc(&ix.d_adj, sizeof(int32_t) * n * ix.R, ix.device_bytes)) != JAG_OK) return st;
+    HIPCHK(hipMemcpy(ix.d_adj, ix.adj.data(), sizeof(int32_t) * n * ix.R, hipMemcpyHostToDevice));
+    if (ix.has_scalar) {
+        if ((st = dalloc(&ix.d_scalar, sizeof(int32_t) * n, ix.device_bytes)) != JAG_OK) return st;
+        HIPCHK(hipMemcpy(ix.d_scalar, ix.scalar.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    }
+    if (ix.has_labels) {
+        std::vector<uint16_t> rows((size_t)n * ix.W, 0xFFFF);
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = ix.loff[i]; j < ix.loff[i + 1]; j++)
+                rows[(size_t)i * ix.W + (j - ix.loff[i])] = (uint16_t)ix.lab[j];
+        if ((st = dalloc(&ix.d_lab, sizeof(uint16_t) * rows.size(), ix.device_bytes)) != JAG_OK) return st;
+        HIPCHK(hipMemcpy(ix.d_lab, rows.data(), sizeof(uint16_t) * rows.size(), hipMemcpyHostToDevice));
+    }
+    // stage FP32 vectors, then lay out the store(s)
+    float *dX = nullptr;
+    HIPCHK(hipMalloc((void **)&dX, sizeof(float) * n * d));
+    hipError_t e = hipMemcpy(dX, ix.X.data(), sizeof(float) * n * d, hipMemcpyHostToDevice);
+    auto cleanup = [&]() { (void)hipFree(dX); };
+    if (e != hipSuccess) {
+        cleanup();
+        set_error("copy of vectors failed: %s", hipGetErrorString(e));
+        return JAG_EDEVICE;
+    }
+    ix.vec_stride = store_row_bytes(ix.store, d);
+    if (pick_group(ix.vec_stride) == 16) ix.vec_stride = (ix.vec_stride + 255) / 256 * 256;
+    if ((st = dalloc(&ix.d_vec, (size_t)n * ix.vec_stride, ix.device_bytes)) != JAG_OK) {
+        cleanup();
+        return st;
+    }
+    const int TB = 256;
+    if (ix.store == JAG_STORE_F32) {
+        int64_t tot = n * (ix.vec_stride / 4);
+        copy_rows_kernel<<<(unsigned)((tot + TB - 1) / TB), TB>>>(dX, n, d, ix.d_vec, ix.vec_stride);
+        ix.d_f32 = ix.d_vec;
+        ix.f32_stride = ix.vec_stride;
+    } else {
+        if (ix.store == JAG_STORE_BF16) {
+            int64_t tot = n * (ix.vec_stride / 2);
+            quant_bf16_kernel<<<(unsigned)((tot + TB - 1) / TB), TB>>>(dX, n, d, ix.d_vec, ix.vec_stride);
+        } else {
+            quant_fp8_kernel<<<(unsigned)n, 64>>>(dX, n, d, ix.d_vec, ix.vec_stride);
+        }
+        if (ix.keep_f32) {
+            ix.f32_stride = (4 * d + 63) / 64 * 64;
+            if ((st = dalloc(&ix.d_f32, (size_t)n * ix.f32_stride, ix.device_bytes)) != JAG_OK) {
+                cleanup();
+                return st;
+            }
+            ix.f32_owned = true;
+            int64_t tot = n * (ix.f32_stride / 4);
+            copy_rows_kernel<<<(unsigned)((tot + TB - 1) / TB), TB>>>(dX, n, d, ix.d_f32, ix.f32_stride);
+        }
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    cleanup();
+    if (e != hipSuccess) {
+        set_error("store layout kernels failed: %s", hipGetErrorString(e));
+        return JAG_EDEVICE;
+    }
+    return JAG_OK;
+}
+
+void free_device(Index &ix)
+{
+    auto f = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    f(ix.d_adj);
+    f(ix.d_scalar);
+    f(ix.d_lab);
+    if (ix.f32_owned) f(ix.d_f32);
+    f(ix.d_vec);
+    f(ix.pred.d_bf16);
+    ix.d_adj = nullptr;
+    ix.d_scalar = nullptr;
+    ix.d_lab = nullptr;
+    ix.d_f32 = nullptr;
+    ix.d_vec = nullptr;
+    ix.pred.d_bf16 = nullptr;
+}
+
+jag_status download_store(const Index &ix, void *rows_out, float *scales_out)
+{
+    const int64_t n = ix.n;
+    const int d = ix.d;
+    std::vector<unsigned char> buf((size_t)n * ix.vec_stride);
+    HIPCHK(hipMemcpy(buf.data(), ix.d_vec, buf.size(), hipMemcpyDeviceToHost));
+    int eb = ix.store == JAG_STORE_F32 ? 4 : ix.store == JAG_STORE_BF16 ? 2 : 1;
+    unsigned char *o = static_cast<unsigned char *>(rows_out);
+    for (int64_t i = 0; i < n; i++) {
+        memcpy(o + (size_t)i * d * eb, buf.data() + (size_t)i * ix.vec_stride, (size_t)d * eb);
+        if (ix.store == JAG_STORE_FP8_E4M3 && scales_out)
+            memcpy(scales_out + i, buf.data() + (size_t)i * ix.vec_stride + ix.vec_stride - 4, 4);
+    }
+    return JAG_OK;
+}
+
+jag_status upload_predictor(Index &ix)
+{
+    if (!ix.pred.d_bf16) {
+        jag_status st = dalloc(&ix.pred.d_bf16, sizeof(uint16_t) * 5376, ix.device_bytes);
+        if (st != JAG_OK) return st;
+    }
+    float *tmp = nullptr;
+    HIPCHK(hipMalloc((void **)&tmp, sizeof(float) * kPredParams));
+    hipError_t e = hipMemcpy(tmp, ix.pred.params.data(), sizeof(float) * kPredParams, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        to_bf16_kernel<<<(kPredParams + 255) / 256, 256>>>(tmp, kPredParams, ix.pred.d_bf16);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        set_error("predictor upload failed: %s", hipGetErrorString(e));
+        return JAG_EDEVICE;
+    }
+    return JAG_OK;
+}
+
+static jag_status fill_args(Index &ix, SearchArgs &a, const float *Q, const void *records, int32_t k,
+                            int32_t *ids, float *dists, int32_t *count)
+{
+    a.adj = ix.d_adj;
+    a.vec = ix.d_vec;
+    a.f32 = ix.d_f32;
+    a.scalar = ix.d_scalar;
+    a.lab = ix.d_lab;
+    a.Q = Q;
+    a.rec = static_cast<const FilterRecord *>(records);
+    a.ids = ids;
+    a.dists = dists;
+    a.count = count;
+    a.stats = nullptr;
+    a.features = nullptr;
+    a.pred = ix.pred.d_bf16;
+    a.vec_stride = ix.vec_stride;
+    a.f32_stride = ix.f32_stride;
+    a.W = ix.W;
+    a.d = ix.d;
+    a.R = ix.R;
+    a.entry = ix.entry;
+    a.k = k;
+    return JAG_OK;
+}
+
+jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
+                         const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
+                         void *stream)
+{
+    if (k < 1 || k > 64 || S.L < k || S.L > 1024 || S.learned < 0 || S.learned > 2 ||
+        S.rerank_mult < 0 || S.rerank_mult * k > 64 || S.max_hops < 0 || nq > INT_MAX) {
+        set_error("need 1 <= k <= 64, k <= L <= 1024, learned in {0,1,2}, rerank_mult*k <= 64");
+        return JAG_EINVAL;
+    }
+    if (S.rerank_mult > 0 && !ix.d_f32) {
+        set_error("reranking needs an FP32 copy (build with keep_f32 or an FP32 store)");
+        return JAG_EUNSUPPORTED;
+    }
+    if (S.learned == 1 && !ix.pred.present) {
+        set_error("learned search needs a predictor (jag_set_predictor)");
+        return JAG_EUNSUPPORTED;
+    }
+    if (S.learned == 2 && !S.features) {
+        set_error("learned == 2 needs a features buffer");
+        return JAG_EINVAL;
+    }
+    int dev;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != ix.device) {
+        set_error("index lives on device %d, current device is %d", ix.device, dev);
+        return JAG_EINVAL;
+    }
+    SearchArgs a;
+    fill_args(ix, a, Q, records, k, ids, dists, count);
+    a.stats = S.stats;
+    a.features = S.features;
+    a.L = S.L;
+    a.mode = S.learned;
+    a.delta = S.delta;
+    a.rerank = S.rerank_mult;
+    a.max_hops = S.max_hops;
+    a.nladder = ix.pred.nladder;
+    a.rho = ix.pred.rho;
+    for (int i = 0; i < JAG_LADDER_MAX; i++) a.ladder[i] = ix.pred.ladder[i];
+    int Lcap = S.L;
+    if (S.learned == 1) {
+        Lcap = ix.pred.ladder[ix.pred.nladder - 1];
+        if (Lcap < k) {
+            set_error("predictor ladder tops out below k");
+            return JAG_EINVAL;
+        }
+        for (int i = 0; i < ix.pred.nladder; i++)
+            if (a.ladder[i] < k) a.ladder[i] = k;
+    }
+    if (S.learned != 0 && Lcap < 1 + 4 * ix.R) Lcap = 1 + 4 * ix.R;
+    Lcap = (Lcap + 63) / 64 * 64;
+    int H = hash_size_for(Lcap);
+    a.Lcap = Lcap;
+    a.Hmask = H - 1;
+    SearchFn fn = pick_search(ix.store, ix.vec_stride);
+    if (!fn) {
+        set_error("no kernel for row stride %d", ix.vec_stride);
+        return JAG_EUNSUPPORTED;
+    }
+    size_t lds = lds_bytes(Lcap, H);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, (hipStream_t)stream, a);
+    HIPCHK(hipGetLastError());
+    return JAG_OK;
+}
+
+jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
+                        int32_t *ids, float *dists, int32_t *count, void *stream)
+{
+    if (k < 1 || k > 64 || nq > INT_MAX) {
+        set_error("need 1 <= k <= 64");
+        return JAG_EINVAL;
+    }
+    if (!ix.d_f32) {
+        set_error("exact search needs the FP32 copy");
+        return JAG_EUNSUPPORTED;
+    }
+    SearchArgs a;
+    fill_args(ix, a, Q, records, k, ids, dists, count);
+    a.Lcap = 64;
+    a.Hmask = 0;
+    int G = pick_group(ix.f32_stride);
+    int ch = ix.f32_stride / (16 * G);
+    ExactFn fn = G == 4 ? exact_for_ch<4>(ch) : exact_for_ch<16>(ch);
+    if (!fn || (G == 16 && ix.f32_stride % 256)) {
+        set_error("no exact kernel for FP32 row stride %d", ix.f32_stride);
+        return JAG_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds_bytes(64, 1), (hipStream_t)stream, a, ix.n);
+    HIPCHK(hipGetLastError());
+    return JAG_OK;
+}
+
+}  // namespace jag
+
+extern "C" jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t nq,
+                                       const jag_filter *F, const int32_t *pool, int64_t pool_len,
+                                       int32_t k, const jag_search_params *S, int32_t *ids,
+                                       float *dists, int32_t *count, void *stream)
+{
+    if (nq == 0) return JAG_OK;
+    if (!idx || !S || nq < 0 || !F) {
+        jag::set_error("null argument");
+        return JAG_EINVAL;
+    }
+    std::vector<jag::FilterRecord> rec(nq);
+    jag_status st = jag_encode_filters(idx, F, nq, pool, pool_len, rec.data());
+    if (st != JAG_OK) return st;
+    void *drec = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMallocAsync(&drec, sizeof(jag::FilterRecord) * nq, s) != hipSuccess) {
+        jag::set_error("device allocation for filter records failed");
+        return JAG_ENOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(drec, rec.data(), sizeof(jag::FilterRecord) * nq, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host staging buffer dies on return
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(drec, s);
+        jag::set_error("filter upload failed: %s", hipGetErrorString(e));
+        return JAG_EDEVICE;
+    }
+    st = jag_search_encoded(idx, Q, nq, drec, k, S, ids, dists, count, stream);
+    (void)hipFreeAsync(drec, s);
+    return st;
+}

@@ -1,0 +1,266 @@
+"""GPU parity: the HIP search through the C ABI against the oracle, on the same
+graph, element by element (see tests/parity.py for the tolerance)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2602_10258_amd import jag
+from workloads import (FILTER_BOOLEAN, FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, encode_filters,
+                       make_config)
+
+from .parity import compare, tau_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_search(idx, Q, F, pool, k, L, learned=0, delta=0.0, rerank_mult=0, max_hops=0,
+               features=False):
+    import torch
+    dev = torch.device("cuda:0")
+    nq = Q.shape[0]
+    rec = jag.jag_encode_filters(idx, F, pool)
+    Qd = torch.from_numpy(np.ascontiguousarray(Q, np.float32)).to(dev)
+    recd = torch.from_numpy(rec).to(dev)
+    ids = torch.full((nq, k), -7, dtype=torch.int32, device=dev)
+    dists = torch.zeros((nq, k), dtype=torch.float32, device=dev)
+    count = torch.full((nq,), -7, dtype=torch.int32, device=dev)
+    stats = torch.zeros((nq, 4), dtype=torch.int32, device=dev)
+    feats = torch.zeros((nq, 16), dtype=torch.float32, device=dev) if features else None
+    sp = jag.SearchParams(L=L, learned=learned, delta=delta, rerank_mult=rerank_mult,
+                          max_hops=max_hops, stats=stats, features=feats)
+    jag.jag_search_encoded(idx, Qd, recd, k, sp, ids, dists, count)
+    torch.cuda.synchronize()
+    out = dict(ids=ids.cpu().numpy(), d2=dists.cpu().numpy(), count=count.cpu().numpy(),
+               stats=stats.cpu().numpy(), rec=rec)
+    if features:
+        out["features"] = feats.cpu().numpy()
+    return out
+
+
+def _index(w, adj, entry, store=jag.STORE_F32, keep_f32=False):
+    return jag.jag_build_from_graph(w.X, adj, entry, scalar=w.scalar, label_off=w.loff,
+                                    labels=w.lab, vocab=w.vocab, store=store, keep_f32=keep_f32)
+
+
+def _valid_fn(w, F, pool):
+    A = O.attrs_of(w)
+
+    def ok(q, ids):
+        df = O.dist_f(A, ids, F, np.full(len(ids), q), pool)
+        return bool(np.all(df == 0))
+    return ok
+
+
+@pytest.mark.parametrize("L", [16, 64, 200])
+def test_c1_fp32_matches_oracle(c1_small, L):
+    w, A, adj, entry = c1_small
+    _say("c1 fp32 L", L)
+    idx = _index(w, adj, entry)
+    g = gpu_search(idx, w.Q, w.F, w.pool, 10, L)
+    orc = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, L, 10)
+    n_ex, n_fl, n_fd = compare(g["ids"], g["d2"], g["count"], orc, tau_for(0, w.d),
+                               _valid_fn(w, w.F, w.pool), f"c1 L={L}")
+    _say(f"exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
+    assert n_ex >= 0.8 * w.nq
+    # expansions equal the oracle's wherever the trajectory is identical
+    same = orc.margin >= tau_for(0, w.d)
+    assert np.array_equal(g["stats"][same, 0], orc.hops[same])
+
+
+@pytest.fixture(scope="module")
+def mixed_world():
+    """6000 points, d = 24 (a ragged row), a scalar and 1-5 labels per item,
+    graph from the oracle builder; 160 queries of all four filter types."""
+    rng = np.random.default_rng(21)
+    w = make_config("c4", n=6000, nq=4)
+    X = (w.X[:, :24] + rng.normal(0, 0.1, size=(6000, 24))).astype(np.float32)
+    sets = [sorted(rng.choice(20, size=rng.integers(1, 6), replace=False).tolist()) for _ in range(6000)]
+    loff = np.zeros(6001, dtype=np.int64)
+    loff[1:] = np.cumsum([len(s) for s in sets])
+    lab = np.array([v for s in sets for v in s], dtype=np.int32)
+    scal = rng.integers(0, 10000, size=6000).astype(np.int32)
+    kinds, pays = [], []
+    for i in range(160):
+        t = i % 4
+        kinds.append(t)
+        if t == FILTER_LABEL:
+            pays.append(int(rng.integers(0, 20)))
+        elif t == FILTER_RANGE:
+            lo = int(rng.integers(0, 10000))
+            pays.append((lo, lo + int(10 ** rng.uniform(0, 4))))
+        elif t == FILTER_SUBSET:
+            pays.append(sorted(rng.choice(20, size=rng.integers(1, 4), replace=False).tolist()))
+        else:
+            a, b, c = rng.choice(20, size=3, replace=False).tolist()
+            pays.append([[a, b], [c]] if i % 8 == 3 else [[a, ~b], [c, b]])
+    F, pool = encode_filters(kinds, pays)
+    Q = (X[rng.integers(0, 6000, size=160)] + rng.normal(0, 0.5, size=(160, 24))).astype(np.float32)
+    from workloads import Workload
+    ww = Workload("mixed", X, Q, F, pool, scal, loff, lab, 20, k=10, R=24, L=64)
+    A = O.attrs_of(ww)
+    adj, entry, _ = O.build(X, A, 24, 48, 1.2, [O.KIND_SCALAR] * 3 + [O.KIND_LABELS],
+                            [1.0, 0.01, 0.0, 0.0], seed=5)
+    return ww, A, adj, entry
+
+
+@pytest.mark.parametrize("L", [10, 48, 130])
+def test_all_filter_types_match_oracle(mixed_world, L):
+    w, A, adj, entry = mixed_world
+    _say("mixed filters L", L)
+    idx = _index(w, adj, entry)
+    g = gpu_search(idx, w.Q, w.F, w.pool, 10, L)
+    orc = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, L, 10)
+    n_ex, n_fl, n_fd = compare(g["ids"], g["d2"], g["count"], orc, tau_for(0, w.d),
+                               _valid_fn(w, w.F, w.pool), f"mixed L={L}")
+    _say(f"exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
+    assert n_ex >= 0.8 * w.nq
+
+
+def test_quantizer_codes_bit_exact():
+    """The device BF16 and FP8 stores hold exactly the oracle encoders' codes."""
+    rng = np.random.default_rng(8)
+    n, d = 3000, 100
+    X = (rng.normal(0, 1, size=(n, d)) * rng.choice([1e-3, 1.0, 50.0], size=(n, 1))).astype(np.float32)
+    X[5] = 0.0
+    X[6, :10] = np.array([448, -448, 449, 1e-9, -1e-9, 2 ** -10, 3 * 2 ** -11, 0.5, 1.0625, -0.0],
+                         dtype=np.float32)
+    # bf16 ties: values halfway between two bf16 codes
+    X[7, :50] = ((rng.integers(0x3F00, 0x4100, size=50).astype(np.uint32) << 16) | 0x8000).view(np.float32)
+    adj = np.full((n, 2), -1, dtype=np.int32)
+    adj[:, 0] = (np.arange(n) + 1) % n
+    _say("quantizer bf16")
+    ib = jag.jag_build_from_graph(X, adj, 0, store=jag.STORE_BF16)
+    rows, _ = jag.jag_get_store(ib)
+    assert np.array_equal(rows, O.bf16_encode(X))
+    _say("quantizer fp8")
+    i8 = jag.jag_build_from_graph(X, adj, 0, store=jag.STORE_FP8_E4M3)
+    codes, scales = jag.jag_get_store(i8)
+    oc, osc = O.fp8_encode_rows(X)
+    assert np.array_equal(scales.view(np.uint32), osc.view(np.uint32))
+    assert np.array_equal(codes, oc)
+
+
+@pytest.mark.parametrize("store", [jag.STORE_BF16, jag.STORE_FP8_E4M3])
+@pytest.mark.parametrize("rerank", [0, 4])
+def test_quantized_search_matches_oracle(c1_small, store, rerank):
+    """Search ranks by the exactly decoded store; reranking rescores the best 4k
+    from the FP32 copy.  The oracle runs on its own decoding of its own codes."""
+    w, A, adj, entry = c1_small
+    _say("quantized store", store, "rerank", rerank)
+    idx = _index(w, adj, entry, store=store, keep_f32=True)
+    if store == jag.STORE_BF16:
+        base = O.bf16_decode(O.bf16_encode(w.X))
+    else:
+        base = O.fp8_decode_rows(*O.fp8_encode_rows(w.X))
+    L = 64
+    g = gpu_search(idx, w.Q, w.F, w.pool, 10, L, rerank_mult=rerank)
+    orc = O.search(base, adj, entry, A, w.Q, w.F, w.pool, L, 10,
+                   rerank=w.X if rerank else None, rerank_mult=rerank or 4)
+    tau = tau_for(store, w.d, rerank_d=w.d if rerank else None)
+    n_ex, n_fl, n_fd = compare(g["ids"], g["d2"], g["count"], orc, tau, _valid_fn(w, w.F, w.pool),
+                               f"store={store} rerank={rerank}")
+    _say(f"exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
+    assert n_ex >= 0.8 * w.nq
+
+
+def test_exact_knn_matches_bruteforce(c1_small):
+    import torch
+    w, A, adj, entry = c1_small
+    _say("exact knn")
+    idx = _index(w, adj, entry)
+    k = 10
+    rec = torch.from_numpy(jag.jag_encode_filters(idx, w.F, w.pool)).cuda()
+    Qd = torch.from_numpy(w.Q).cuda()
+    ids = torch.empty((w.nq, k), dtype=torch.int32, device="cuda")
+    dd = torch.empty((w.nq, k), dtype=torch.float32, device="cuda")
+    cnt = torch.empty((w.nq,), dtype=torch.int32, device="cuda")
+    jag.jag_exact_knn(idx, Qd, rec, k, ids, dd, cnt)
+    torch.cuda.synchronize()
+    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, k + 1)
+    ids = ids.cpu().numpy()
+    tau = tau_for(0, w.d)
+    for q in range(w.nq):
+        gaps = np.diff(gd[q]) / np.maximum(gd[q, 1:], 1e-30)
+        if np.all(gaps >= tau):
+            assert np.array_equal(ids[q], gi[q, :k]), q
+    assert np.array_equal(cnt.cpu().numpy(), np.minimum(nv, k))
+
+
+def test_edge_cases(mixed_world):
+    import torch
+    w, A, adj, entry = mixed_world
+    idx = _index(w, adj, entry)
+    _say("edge: empty batch")
+    g = gpu_search(idx, w.Q[:0], w.F[:0], w.pool, 10, 32)
+    assert g["ids"].shape == (0, 10)
+    _say("edge: unsatisfiable, empty and single-item filters, L = k, one hop")
+    F, pool = encode_filters([FILTER_BOOLEAN, FILTER_RANGE, FILTER_RANGE, FILTER_LABEL],
+                             [[[3, ~3]], (20000, 30000), (int(w.scalar[17]), int(w.scalar[17])), 5])
+    Q = w.X[[1, 2, 17, 4]]
+    g = gpu_search(idx, Q, F, pool, 10, 10)
+    orc = O.search(w.X, adj, entry, A, Q, F, pool, 10, 10)
+    assert g["count"][0] == 0 and np.all(g["ids"][0] == -1) and np.all(np.isinf(g["d2"][0]))
+    assert g["count"][1] == 0
+    assert np.array_equal(g["ids"][2:], orc.ids[2:]) or np.any(orc.margin[2:] < tau_for(0, w.d))
+    g1 = gpu_search(idx, Q, F, pool, 10, 32, max_hops=1)
+    assert np.all(g1["stats"][:, 0] <= 1)
+    _say("edge: ragged batch of 37 and k = 1")
+    g = gpu_search(idx, w.Q[:37], w.F[:37], w.pool, 1, 16)
+    orc = O.search(w.X, adj, entry, A, w.Q[:37], w.F[:37], w.pool, 16, 1)
+    compare(g["ids"], g["d2"], g["count"], orc, tau_for(0, w.d), None, "k=1")
+    _say("edge: argument errors")
+    with pytest.raises(jag.JagError) as e:
+        gpu_search(idx, w.Q[:4], w.F[:4], w.pool, 10, 8)  # L < k
+    assert e.value.status == jag.JAG_EINVAL
+    with pytest.raises(jag.JagError):
+        gpu_search(idx, w.Q[:4], w.F[:4], w.pool, 10, 2000)  # L too large
+    with pytest.raises(jag.JagError):
+        gpu_search(idx, w.Q[:4], w.F[:4], w.pool, 10, 32, rerank_mult=7)  # 7 * k > 64
+    ib = _index(w, adj, entry, store=jag.STORE_BF16, keep_f32=False)
+    with pytest.raises(jag.JagError) as e:
+        gpu_search(ib, w.Q[:4], w.F[:4], w.pool, 10, 32, rerank_mult=4)  # no FP32 copy
+    assert e.value.status == jag.JAG_EUNSUPPORTED
+    with pytest.raises(jag.JagError) as e:
+        gpu_search(idx, w.Q[:4], w.F[:4], w.pool, 10, 32, learned=1)  # no predictor
+    assert e.value.status == jag.JAG_EUNSUPPORTED
+    Fbad, pbad = encode_filters([FILTER_LABEL], [99])
+    with pytest.raises(jag.JagError):
+        jag.jag_encode_filters(idx, Fbad, pbad)
+
+
+def test_save_load_roundtrip(mixed_world, tmp_path):
+    w, A, adj, entry = mixed_world
+    _say("save / load")
+    idx = _index(w, adj, entry, store=jag.STORE_BF16, keep_f32=True)
+    p = str(tmp_path / "ix.jag")
+    jag.jag_save(idx, p)
+    idx2 = jag.jag_load(p)
+    i1, i2 = idx.info(), idx2.info()
+    assert (i1.n, i1.d, i1.R, i1.entry, i1.store, i1.has_f32) == (i2.n, i2.d, i2.R, i2.entry, i2.store, i2.has_f32)
+    a2, e2 = jag.jag_get_graph(idx2)
+    assert e2 == entry and np.array_equal(a2, adj)
+    g1 = gpu_search(idx, w.Q, w.F, w.pool, 10, 48, rerank_mult=4)
+    g2 = gpu_search(idx2, w.Q, w.F, w.pool, 10, 48, rerank_mult=4)
+    assert np.array_equal(g1["ids"], g2["ids"]) and np.array_equal(g1["d2"], g2["d2"])
+
+
+def test_repeat_and_shuffle_give_identical_results(mixed_world):
+    """Queries share no state: the same query gives the same answer alone, in a
+    batch, and in any order."""
+    w, A, adj, entry = mixed_world
+    idx = _index(w, adj, entry)
+    g = gpu_search(idx, w.Q, w.F, w.pool, 10, 48)
+    perm = np.random.default_rng(3).permutation(w.nq)
+    F2 = w.F[perm]
+    gp = gpu_search(idx, w.Q[perm], F2, w.pool, 10, 48)
+    assert np.array_equal(gp["ids"], g["ids"][perm])
+    one = gpu_search(idx, w.Q[5:6], w.F[5:6], w.pool, 10, 48)
+    assert np.array_equal(one["ids"][0], g["ids"][5])

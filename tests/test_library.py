@@ -1,0 +1,96 @@
+"""CPU checks of the product library: it loads, exports every entry point the
+header declares, rejects bad arguments, and its host-only graph builder
+produces a valid, deterministic, useful graph."""
+import collections
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2602_10258_amd import jag
+from workloads import make_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    src = open(os.path.join(ROOT, "include", "jag.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:jag_status|void|const char \*)\s*(jag_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_header_symbol():
+    L = jag.lib()
+    syms = _header_symbols()
+    assert len(syms) >= 18
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) <= set(jag.exported_symbols()) | {"jag_free"}
+    assert b"gfx950" in L.jag_version()
+
+
+def test_build_graph_rejects_bad_arguments():
+    X = np.zeros((10, 4), np.float32)
+    with pytest.raises(jag.JagError) as e:
+        jag.jag_build_graph(X, R=0)
+    assert e.value.status == jag.JAG_EINVAL
+    with pytest.raises(jag.JagError):  # thresholds name a scalar attribute that is absent
+        jag.jag_build_graph(X, R=4, thresholds=[(jag.ATTR_SCALAR, 0.5)])
+    with pytest.raises(jag.JagError):  # unsorted label rows
+        jag.jag_build_graph(X, label_off=np.array([0, 2] + [2] * 9), labels=np.array([3, 1]),
+                            vocab=4, R=4, thresholds=[(jag.ATTR_LABELS, 0.0)])
+    with pytest.raises(jag.JagError):  # label outside the vocabulary
+        jag.jag_build_graph(X, label_off=np.arange(11), labels=np.full(10, 9), vocab=4, R=4,
+                            thresholds=[(jag.ATTR_LABELS, 0.0)])
+    Xn = X.copy()
+    Xn[3, 2] = np.nan
+    with pytest.raises(jag.JagError):
+        jag.jag_build_graph(Xn, R=4, thresholds=[(jag.ATTR_SCALAR, 1.0)], scalar=np.zeros(10))
+
+
+def _reach(adj, s):
+    seen = {s}
+    dq = collections.deque([s])
+    while dq:
+        u = dq.popleft()
+        for v in adj[u]:
+            if v >= 0 and v not in seen:
+                seen.add(int(v))
+                dq.append(int(v))
+    return len(seen)
+
+
+def test_host_builder_structure_determinism_and_recall():
+    """The product builder is parity unpinned (no reference graph): structure,
+    determinism across thread counts, and recall through the oracle's search."""
+    w = make_config("c1")
+    kw = dict(label_off=w.loff, labels=w.lab, vocab=8, R=32, L_build=64,
+              thresholds=[(jag.ATTR_LABELS, 1.0), (jag.ATTR_LABELS, 0.0)], seed=0)
+    adj, entry = jag.jag_build_graph(w.X, n_threads=8, **kw)
+    adj1, entry1 = jag.jag_build_graph(w.X, n_threads=1, **kw)
+    assert entry == entry1 and np.array_equal(adj, adj1)
+    deg = (adj >= 0).sum(1)
+    assert deg.max() <= 32 and deg.min() >= 1
+    for i in range(0, w.n, 101):
+        row = adj[i][:deg[i]]
+        assert i not in row.tolist() and len(set(row.tolist())) == deg[i]
+        assert np.all(adj[i][deg[i]:] == -1)
+    assert _reach(adj, entry) >= 0.999 * w.n
+    A = O.attrs_of(w)
+    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, 10, nthreads=4)
+    r = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, 64, 10)
+    assert np.nanmean(O.recall_at_k(r.ids, gi, gd, nv, 10)) >= 0.95
+
+
+def test_host_builder_range_and_labelsets():
+    w = make_config("c4", n=3000, nq=60)
+    adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=8,
+                                     R=24, thresholds=[(jag.ATTR_SCALAR, 1.0), (jag.ATTR_SCALAR, 0.01),
+                                                       (jag.ATTR_SCALAR, 0.0), (jag.ATTR_LABELS, 0.0)],
+                                     seed=1)
+    assert (adj >= 0).sum(1).max() <= 24
+    A = O.attrs_of(w)
+    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, 10)
+    r = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, 128, 10)
+    assert np.nanmean(O.recall_at_k(r.ids, gi, gd, nv, 10)) >= 0.9
