@@ -320,6 +320,52 @@ def _c1_centers(seed: int) -> np.ndarray:
     return rng.normal(0.0, 4.0, size=(16, 32))
 
 
+_SHAPES = {"c1": (32, 16), "c2": (96, 256), "c3": (128, 256), "c4": (32, 16), "c5": (100, 1024)}
+
+
+def extra_queries(w: Workload, nq: int, qseed: int, seed: int = 0):
+    """A further query set with the recipe of workload ``w`` (same mixture
+    centres, different seed), e.g. for fitting the beam predictor.
+    Returns (Q, F, pool)."""
+    d, clusters = _SHAPES[w.name]
+    centers = np.random.default_rng(seed).normal(0.0, 4.0, size=(clusters, d))
+    rq = np.random.default_rng(qseed)
+    Q, _ = mixture(rq, nq, d, clusters, centers=centers)
+    if w.name == "c1":
+        F, pool = encode_filters([FILTER_LABEL] * nq, rq.integers(0, 8, size=nq).tolist())
+    elif w.name == "c2":
+        lo, hi = range_filters(rq, nq)
+        F, pool = encode_filters([FILTER_RANGE] * nq, list(zip(lo.tolist(), hi.tolist())))
+    elif w.name == "c3":
+        kinds, pays = _subset_and_bool_queries(rq, nq // 2, nq - nq // 2, 1000)
+        F, pool = encode_filters(kinds, pays)
+    else:
+        kinds, pays = [], []
+        lo, hi = range_filters(rq, nq)
+        vocab = w.vocab
+        ntypes = 3 if w.name == "c4" else 4
+        t = rq.integers(0, ntypes, size=nq)
+        for i in range(nq):
+            if t[i] == FILTER_LABEL:
+                kinds.append(FILTER_LABEL)
+                pays.append(int(rq.integers(0, 8)) if w.name == "c4" else _distinct_zipf(rq, vocab, 1)[0])
+            elif t[i] == FILTER_RANGE:
+                kinds.append(FILTER_RANGE)
+                pays.append((int(lo[i]), int(hi[i])))
+            elif t[i] == FILTER_SUBSET:
+                kinds.append(FILTER_SUBSET)
+                if w.name == "c4":
+                    pays.append(sorted(rq.choice(8, size=int(rq.integers(1, 3)), replace=False).tolist()))
+                else:
+                    pays.append(sorted(_distinct_zipf(rq, vocab, int(rq.integers(1, 4)))))
+            else:
+                a, b, c = _distinct_zipf(rq, vocab, 3)
+                kinds.append(FILTER_BOOLEAN)
+                pays.append([[a, b], [c]])
+        F, pool = encode_filters(kinds, pays)
+    return Q, F, pool
+
+
 def poisson_arrivals(rng: np.random.Generator, nq: int, qps: float) -> np.ndarray:
     """Arrival times (seconds) of a Poisson stream at rate ``qps``."""
     return np.cumsum(rng.exponential(1.0 / qps, size=nq))
