@@ -46,12 +46,13 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override the number of vectors")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--ntrain", type=int, default=20000)
-    ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-fixed", action="store_true")
     ap.add_argument("--profile-op", action="store_true",
                     help="run only the operating point (for rocprofv3); needs --L and --store")
-    ap.add_argument("--L", type=int, default=0)
+    ap.add_argument("--L", type=int, default=48)
+    ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
     return ap.parse_args()
 
 
@@ -123,6 +124,15 @@ def main():
     cnt = torch.empty((nq,), dtype=torch.int32, device=dev)
     stats = torch.zeros((nq, 4), dtype=torch.int32, device=dev)
 
+    if args.profile_op:
+        # only the operating point, for rocprofv3 (no sweeps, no ground truth)
+        sp = jag.SearchParams(L=args.L)
+        for i in range(args.warmup + args.steps):
+            jag.jag_search_encoded(ix32, Qd, rec32, k, sp, ids, d2, cnt)
+        torch.cuda.synchronize()
+        log(f"profiled {args.steps} steps of fp32 L={args.L}")
+        return
+
     # ---- ground truth: the oracle's exact filtered k-NN in FP64
     from oracle import oracle as O
     t2 = time.time()
@@ -170,7 +180,8 @@ def main():
     if not args.only_fixed:
         t3 = time.time()
         Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
-        P, rho, fit_rep = pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32)
+        P, rho, fit_rep = pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4,
+                                   dump=args.dump_traces)
         log(f"predictor fitted on {fit_rep.n_train} traces in {time.time() - t3:.1f}s: loss "
             f"{fit_rep.loss_first:.3f} -> {fit_rep.loss_last:.3f}, rho={rho:.2f}, "
             f"unreachable={fit_rep.unreachable}")

@@ -129,6 +129,10 @@ typedef struct {
     int32_t *stats;      /* optional device int32 [nq][4]: expansions, vector distances,
                             attribute evaluations, chosen beam (learned) or L */
     float *features;     /* learned == 2: device float [nq][16] predictor features */
+    int32_t hash_log2;   /* 0 = automatic; else 10..13: the per-query LDS table of
+                            discovered ids has 2^hash_log2 slots.  It only trades LDS
+                            (occupancy) against repeated evaluations; results do not
+                            depend on it. */
 } jag_search_params;
 
 typedef struct {

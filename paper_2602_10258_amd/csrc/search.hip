@@ -973,8 +973,10 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
                          void *stream)
 {
     if (k < 1 || k > 64 || S.L < k || S.L > 1024 || S.learned < 0 || S.learned > 2 ||
-        S.rerank_mult < 0 || S.rerank_mult * k > 64 || S.max_hops < 0 || nq > INT_MAX) {
-        set_error("need 1 <= k <= 64, k <= L <= 1024, learned in {0,1,2}, rerank_mult*k <= 64");
+        S.rerank_mult < 0 || S.rerank_mult * k > 64 || S.max_hops < 0 || nq > INT_MAX ||
+        (S.hash_log2 != 0 && (S.hash_log2 < 10 || S.hash_log2 > 13))) {
+        set_error("need 1 <= k <= 64, k <= L <= 1024, learned in {0,1,2}, rerank_mult*k <= 64, "
+                  "hash_log2 in {0, 10..13}");
         return JAG_EINVAL;
     }
     if (S.rerank_mult > 0 && !ix.d_f32) {
@@ -1019,7 +1021,10 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     }
     if (S.learned != 0 && Lcap < 1 + 4 * ix.R) Lcap = 1 + 4 * ix.R;
     Lcap = (Lcap + 63) / 64 * 64;
-    int H = hash_size_for(Lcap);
+    // the table of discovered ids is sized by the working beam: in learned
+    // mode the beam after the fourth expansion, typically far below Lcap
+    int Lwork = S.learned == 1 ? ix.pred.ladder[ix.pred.nladder / 2] : S.L;
+    int H = S.hash_log2 ? (1 << S.hash_log2) : hash_size_for(Lwork);
     a.Lcap = Lcap;
     a.Hmask = H - 1;
     SearchFn fn = pick_search(ix.store, ix.vec_stride);

@@ -50,7 +50,7 @@ def _device_batch(idx, Q, F, pool):
     return Qd, rec
 
 
-def traces(idx, Qd, rec, k: int, ladder=LADDER):
+def traces(idx, Qd, rec, k: int, ladder=LADDER, rerank_mult: int = 0):
     """Features (nq x 16), per-ladder answers (nl x nq x k) and expansions (nl x nq)."""
     import torch
     nq = Qd.shape[0]
@@ -61,7 +61,8 @@ def traces(idx, Qd, rec, k: int, ladder=LADDER):
     cnt = torch.empty((nq,), dtype=torch.int32, device="cuda")
     all_ids, hops = [], []
     for L in ladder:
-        sp = jag.SearchParams(L=int(max(L, k)), learned=2, stats=stats, features=feats)
+        sp = jag.SearchParams(L=int(max(L, k)), learned=2, stats=stats, features=feats,
+                              rerank_mult=rerank_mult)
         jag.jag_search_encoded(idx, Qd, rec, k, sp, ids, d2, cnt)
         torch.cuda.synchronize()
         all_ids.append(ids.cpu().numpy().copy())
@@ -101,16 +102,21 @@ def targets_from(all_ids, exact_ids, exact_cnt, k: int, need: float = 0.95):
 
 
 def fit(idx, Q, F, pool, k: int = 10, epochs: int = 40, batch: int = 512, lr: float = 3e-3,
-        seed: int = 0, ladder=LADDER, exact_idx=None) -> tuple[np.ndarray, float, FitReport]:
+        seed: int = 0, ladder=LADDER, exact_idx=None, rerank_mult: int = 0,
+        dump: str | None = None) -> tuple[np.ndarray, float, FitReport]:
     """Train on (Q, F) and attach the predictor to ``idx``.  ``exact_idx`` is an
-    index over the same data holding an FP32 copy (defaults to ``idx``)."""
+    index over the same data holding an FP32 copy (defaults to ``idx``);
+    ``rerank_mult`` must match the setting the learned search will use."""
     import torch
     Qd, rec = _device_batch(idx, Q, F, pool)
     ex = exact_idx if exact_idx is not None else idx
     Qe, rece = (Qd, rec) if ex is idx else _device_batch(ex, Q, F, pool)
     exact_ids, exact_cnt = exact_answers(ex, Qe, rece, k)
-    feats, all_ids, hops = traces(idx, Qd, rec, k, ladder)
+    feats, all_ids, hops = traces(idx, Qd, rec, k, ladder, rerank_mult)
     tgt, reached = targets_from(all_ids, exact_ids, exact_cnt, k)
+    if dump:
+        np.savez_compressed(dump, features=feats, targets=tgt, reached=reached, hops=hops,
+                            ladder=ladder)
     ok = feats[:, 15] == 1.0  # rows with four expansions
     X = torch.from_numpy(np.ascontiguousarray(feats[ok])).cuda()
     T = torch.from_numpy(tgt[ok].astype(np.float32)).cuda()
