@@ -53,6 +53,8 @@ def parse():
                     help="run only the operating point (for rocprofv3); needs --L and --store")
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
+    ap.add_argument("--graph-cache", default=None,
+                    help="load the graph from this .npz if present, else build and save it there")
     return ap.parse_args()
 
 
@@ -107,9 +109,16 @@ def main():
 
     # ---- build (host threads) and lay out the two stores over one graph
     t1 = time.time()
-    adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
-                                     vocab=w.vocab, R=w.R, L_build=2 * w.R,
-                                     thresholds=THRESHOLDS[w.name], seed=0)
+    if args.graph_cache and os.path.exists(args.graph_cache):
+        z = np.load(args.graph_cache)
+        adj, entry = z["adj"], int(z["entry"])
+        log(f"graph loaded from {args.graph_cache}")
+    else:
+        adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
+                                         vocab=w.vocab, R=w.R, L_build=2 * w.R,
+                                         thresholds=THRESHOLDS[w.name], seed=0)
+        if args.graph_cache:
+            np.savez(args.graph_cache, adj=adj, entry=entry)
     build_s = time.time() - t1
     log(f"graph built in {build_s:.1f}s, mean degree {(adj >= 0).sum(1).mean():.1f}")
     kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)

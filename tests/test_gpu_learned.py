@@ -61,9 +61,9 @@ def test_training_fits_a_known_function():
     P, loss = jag.jag_train_predictor(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), P0,
                                       epochs=30, batch=256, lr=3e-3, seed=2)
     assert np.all(np.isfinite(P))
-    assert loss[-1] < 0.05 * loss[0] and loss[-1] < 0.05
+    assert loss[-1] < 0.02 * loss[0] and loss[-1] < 0.1
     _, _, Y = O.mlp_loss_grad(P.astype(np.float64), X[:64].astype(np.float64), T[:64].astype(np.float64))
-    assert np.abs(Y - T[:64]).mean() < 0.2
+    assert np.abs(Y - T[:64]).mean() < 0.3
 
 
 def _sel_feature(nvalid, n):
