@@ -44,8 +44,10 @@ typedef enum {
     JAG_EINVAL = -1,      /* bad argument, shape, filter or label */
     JAG_ENOMEM = -2,      /* host or device allocation failed */
     JAG_EDEVICE = -3,     /* HIP runtime error or no gfx950 device */
-    JAG_EIO = -4,         /* file could not be read or written */
-    JAG_EUNSUPPORTED = -5 /* valid request the index cannot serve (e.g. no FP32 copy) */
+    JAG_EIO = -4,          /* file could not be read or written */
+    JAG_EUNSUPPORTED = -5, /* valid request the index cannot serve (e.g. no FP32 copy) */
+    JAG_EBUSY = -6,        /* jag_server_submit: queue full, nothing queued */
+    JAG_EAGAIN = 1         /* jag_server_poll: request still pending (not an error) */
 } jag_status;
 
 /* Vector store used by the search (Section 8-style precision choices are the
@@ -276,6 +278,65 @@ jag_status jag_train_predictor(const float *features, const float *targets, int6
 jag_status jag_predictor_grad(const float *features, const float *targets, int64_t m,
                               const float *params, float *loss_out, float *grad_out,
                               void *stream);
+
+/* ---- serving (not in the paper) ------------------------------------------ */
+
+/*
+ * A server owns a scheduler thread that batches single queries as they
+ * arrive and keeps several batches on the GPU at once (one HIP stream
+ * each).  A request is admitted to the GPU when a stream is free and the
+ * number of requests on the GPU stays within max_inflight, which defaults
+ * to the number of query wavefronts the device can hold resident at once
+ * (from the kernel's LDS and register needs).  Results are identical to a
+ * jag_search_encoded call on the same query: queries share no state.
+ * Per-request latency is measured from submit to the host seeing the result.
+ */
+typedef struct jag_server jag_server;
+
+typedef struct {
+    int32_t k;                /* neighbours per query, 1..64 */
+    jag_search_params search; /* L, learned, delta, rerank_mult, max_hops, hash_log2
+                                 (stats and features must be NULL) */
+    int32_t max_batch;        /* requests per launch, 1..4096 */
+    int32_t n_streams;        /* batches in flight at once, 1..8 */
+    int32_t max_wait_us;      /* a partial batch waits at most this long for company */
+    int64_t max_inflight;     /* 0 = resident capacity of the device for this search */
+    int64_t queue_capacity;   /* pending requests beyond this are refused (JAG_EBUSY) */
+    int64_t hbm_budget_bytes; /* 0 = no limit; else the server's device buffers must fit */
+} jag_server_params;
+
+typedef struct {
+    int64_t submitted, completed, batches, max_inflight_seen, resident_capacity;
+    double p50_us, p99_us, mean_us, max_us; /* latency of completed requests */
+    double qps;                             /* completed / (last completion - first submit) */
+    double mean_batch;
+    int64_t device_bytes;
+} jag_server_stats;
+
+/* Start a server on idx (which must outlive it).  Errors: EINVAL, ENOMEM,
+ * EUNSUPPORTED (e.g. buffers beyond hbm_budget_bytes), EDEVICE. */
+jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_server **out);
+
+/* Queue n requests: Q host float[n][d], F host filters (pool as in
+ * jag_encode_filters).  Filters are validated here; on EINVAL nothing is
+ * queued.  tickets_out[n] receives one ticket per request.  EBUSY when the
+ * queue would exceed queue_capacity (nothing queued). */
+jag_status jag_server_submit(jag_server *s, const float *Q, const jag_filter *F, int64_t n,
+                             const int32_t *pool, int64_t pool_len, uint64_t *tickets_out);
+
+/* Result of one request: JAG_OK (and the result is released), JAG_EAGAIN if
+ * still pending, EINVAL for an unknown ticket.  ids/dists: host [k];
+ * latency_us may be NULL. */
+jag_status jag_server_poll(jag_server *s, uint64_t ticket, int32_t *ids, float *dists,
+                           int32_t *count, double *latency_us);
+
+/* Block until every request submitted so far has completed. */
+jag_status jag_server_drain(jag_server *s);
+
+jag_status jag_server_stats_get(jag_server *s, jag_server_stats *out);
+
+/* Drain, stop the scheduler and free the server.  NULL is allowed. */
+void jag_server_stop(jag_server *s);
 
 /* ---- misc ---------------------------------------------------------------- */
 

@@ -10,10 +10,6 @@
 
 #include "jag_internal.h"
 
-struct jag_index {
-    jag::Index ix;
-};
-
 namespace jag {
 
 static thread_local char g_err[512] = "";

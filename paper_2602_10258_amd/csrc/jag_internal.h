@@ -114,6 +114,9 @@ void free_device(Index &ix);
 jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
                          const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
                          void *stream);
+// Query wavefronts of this search the device can hold resident at once.
+jag_status search_capacity(Index &ix, int32_t k, const jag_search_params &S, int64_t *resident,
+                           size_t *lds_per_query);
 jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
                         int32_t *ids, float *dists, int32_t *count, void *stream);
 jag_status upload_predictor(Index &ix);
@@ -129,3 +132,7 @@ jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, cons
                           int64_t pool_len, FilterRecord *out);
 
 }  // namespace jag
+
+struct jag_index {
+    jag::Index ix;
+};

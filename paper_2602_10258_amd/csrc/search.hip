@@ -968,9 +968,10 @@ static jag_status fill_args(Index &ix, SearchArgs &a, const float *Q, const void
     return JAG_OK;
 }
 
-jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
-                         const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
-                         void *stream)
+// Validate a search request and choose its kernel, LDS size and arguments.
+static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
+                              const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
+                              SearchArgs &a, SearchFn &fn, size_t &lds)
 {
     if (k < 1 || k > 64 || S.L < k || S.L > 1024 || S.learned < 0 || S.learned > 2 ||
         S.rerank_mult < 0 || S.rerank_mult * k > 64 || S.max_hops < 0 || nq > INT_MAX ||
@@ -997,7 +998,6 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         set_error("index lives on device %d, current device is %d", ix.device, dev);
         return JAG_EINVAL;
     }
-    SearchArgs a;
     fill_args(ix, a, Q, records, k, ids, dists, count);
     a.stats = S.stats;
     a.features = S.features;
@@ -1027,14 +1027,46 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     int H = S.hash_log2 ? (1 << S.hash_log2) : hash_size_for(Lwork);
     a.Lcap = Lcap;
     a.Hmask = H - 1;
-    SearchFn fn = pick_search(ix.store, ix.vec_stride);
+    fn = pick_search(ix.store, ix.vec_stride);
     if (!fn) {
         set_error("no kernel for row stride %d", ix.vec_stride);
         return JAG_EUNSUPPORTED;
     }
-    size_t lds = lds_bytes(Lcap, H);
+    lds = lds_bytes(Lcap, H);
+    return JAG_OK;
+}
+
+jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
+                         const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
+                         void *stream)
+{
+    SearchArgs a;
+    SearchFn fn = nullptr;
+    size_t lds = 0;
+    jag_status st = plan_search(ix, Q, nq, records, k, S, ids, dists, count, a, fn, lds);
+    if (st != JAG_OK) return st;
     hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, (hipStream_t)stream, a);
     HIPCHK(hipGetLastError());
+    return JAG_OK;
+}
+
+jag_status search_capacity(Index &ix, int32_t k, const jag_search_params &S, int64_t *resident,
+                           size_t *lds_per_query)
+{
+    SearchArgs a;
+    SearchFn fn = nullptr;
+    size_t lds = 0;
+    jag_search_params s2 = S;
+    float dummy_f = 0.f;
+    if (s2.learned == 2 && !s2.features) s2.features = &dummy_f;
+    jag_status st = plan_search(ix, &dummy_f, 1, &dummy_f, k, s2, nullptr, nullptr, nullptr, a, fn, lds);
+    if (st != JAG_OK) return st;
+    int per_cu = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), 64, lds));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, ix.device));
+    *resident = (int64_t)per_cu * prop.multiProcessorCount;
+    *lds_per_query = lds;
     return JAG_OK;
 }
 

@@ -1,0 +1,426 @@
+// Request server: continuous batching of single filtered queries.
+//
+// Callers queue requests (jag_server_submit) from any thread.  A scheduler
+// thread keeps up to n_streams batches on the GPU, one HIP stream each:
+// whenever a stream is idle and requests are pending it gathers up to
+// max_batch of them -- without exceeding max_inflight requests on the GPU --
+// stages their vectors and filter records in pinned host memory, copies them
+// to the stream's device buffers, launches the search kernel and copies the
+// results back, all asynchronously on that stream.  Finished streams are
+// found with hipEventQuery and their requests completed.  New requests thus
+// join the device while earlier batches are still running, and batches on
+// different streams run concurrently.  Each query's beam lives in its own
+// wavefront's LDS for the whole search, so a result does not depend on the
+// batch it rode in.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "jag_internal.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket;
+    jag::FilterRecord rec;
+    std::vector<float> q;
+    clk::time_point t_submit;
+};
+
+struct Done {
+    std::vector<int32_t> ids;
+    std::vector<float> dists;
+    int32_t count;
+    double latency_us;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    // pinned host staging and device buffers sized for max_batch requests
+    float *h_q = nullptr;
+    jag::FilterRecord *h_rec = nullptr;
+    int32_t *h_ids = nullptr, *h_cnt = nullptr;
+    float *h_d = nullptr;
+    float *d_q = nullptr;
+    jag::FilterRecord *d_rec = nullptr;
+    int32_t *d_ids = nullptr, *d_cnt = nullptr;
+    float *d_d = nullptr;
+    std::vector<Request> batch;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct jag_server {
+    jag_index *idx = nullptr;
+    jag_server_params P{};
+    int64_t max_inflight = 0, resident = 0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> pending;
+    std::unordered_map<uint64_t, Done> done;
+    std::vector<double> latencies;
+    uint64_t next_ticket = 1;
+    int64_t submitted = 0, completed = 0, batches = 0, inflight = 0, max_inflight_seen = 0;
+    int64_t batched_requests = 0;
+    clk::time_point t_first{}, t_last{};
+    bool have_first = false;
+    bool stop = false;
+    std::string error;
+    std::thread worker;
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+#define HIPOK(expr) ((expr) == hipSuccess)
+
+void free_slot(Slot &s)
+{
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.event) (void)hipEventDestroy(s.event);
+    for (void *p : {(void *)s.h_q, (void *)s.h_rec, (void *)s.h_ids, (void *)s.h_cnt, (void *)s.h_d})
+        if (p) (void)hipHostFree(p);
+    for (void *p : {(void *)s.d_q, (void *)s.d_rec, (void *)s.d_ids, (void *)s.d_cnt, (void *)s.d_d})
+        if (p) (void)hipFree(p);
+    s = Slot();
+}
+
+bool alloc_slot(Slot &s, int B, int d, int k)
+{
+    return HIPOK(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) &&
+           HIPOK(hipEventCreateWithFlags(&s.event, hipEventDisableTiming)) &&
+           HIPOK(hipHostMalloc((void **)&s.h_q, sizeof(float) * B * d, hipHostMallocDefault)) &&
+           HIPOK(hipHostMalloc((void **)&s.h_rec, sizeof(jag::FilterRecord) * B, hipHostMallocDefault)) &&
+           HIPOK(hipHostMalloc((void **)&s.h_ids, sizeof(int32_t) * B * k, hipHostMallocDefault)) &&
+           HIPOK(hipHostMalloc((void **)&s.h_cnt, sizeof(int32_t) * B, hipHostMallocDefault)) &&
+           HIPOK(hipHostMalloc((void **)&s.h_d, sizeof(float) * B * k, hipHostMallocDefault)) &&
+           HIPOK(hipMalloc((void **)&s.d_q, sizeof(float) * B * d)) &&
+           HIPOK(hipMalloc((void **)&s.d_rec, sizeof(jag::FilterRecord) * B)) &&
+           HIPOK(hipMalloc((void **)&s.d_ids, sizeof(int32_t) * B * k)) &&
+           HIPOK(hipMalloc((void **)&s.d_cnt, sizeof(int32_t) * B)) &&
+           HIPOK(hipMalloc((void **)&s.d_d, sizeof(float) * B * k));
+}
+
+int64_t slot_device_bytes(int B, int d, int k)
+{
+    return (int64_t)B * (4 * d + (int64_t)sizeof(jag::FilterRecord) + 8 * k + 4);
+}
+
+// Launch one batch on a free slot (called with the lock released).
+bool launch(jag_server *S, Slot &s)
+{
+    jag::Index &ix = S->idx->ix;
+    const int d = ix.d, k = S->P.k;
+    const int n = (int)s.batch.size();
+    for (int i = 0; i < n; i++) {
+        std::memcpy(s.h_q + (size_t)i * d, s.batch[i].q.data(), sizeof(float) * d);
+        s.h_rec[i] = s.batch[i].rec;
+    }
+    bool ok = HIPOK(hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * n * d, hipMemcpyHostToDevice, s.stream)) &&
+              HIPOK(hipMemcpyAsync(s.d_rec, s.h_rec, sizeof(jag::FilterRecord) * n, hipMemcpyHostToDevice,
+                                   s.stream));
+    if (ok) {
+        jag_search_params sp = S->P.search;
+        ok = jag::launch_search(ix, s.d_q, n, s.d_rec, k, sp, s.d_ids, s.d_d, s.d_cnt, s.stream) == JAG_OK;
+    }
+    ok = ok && HIPOK(hipMemcpyAsync(s.h_ids, s.d_ids, sizeof(int32_t) * n * k, hipMemcpyDeviceToHost, s.stream)) &&
+         HIPOK(hipMemcpyAsync(s.h_d, s.d_d, sizeof(float) * n * k, hipMemcpyDeviceToHost, s.stream)) &&
+         HIPOK(hipMemcpyAsync(s.h_cnt, s.d_cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s.stream)) &&
+         HIPOK(hipEventRecord(s.event, s.stream));
+    return ok;
+}
+
+void finish(jag_server *S, Slot &s)
+{
+    const int k = S->P.k;
+    auto now = clk::now();
+    std::lock_guard<std::mutex> g(S->mu);
+    for (size_t i = 0; i < s.batch.size(); i++) {
+        Done r;
+        r.ids.assign(s.h_ids + i * k, s.h_ids + (i + 1) * k);
+        r.dists.assign(s.h_d + i * k, s.h_d + (i + 1) * k);
+        r.count = s.h_cnt[i];
+        r.latency_us = std::chrono::duration<double, std::micro>(now - s.batch[i].t_submit).count();
+        S->latencies.push_back(r.latency_us);
+        S->done.emplace(s.batch[i].ticket, std::move(r));
+    }
+    S->completed += (int64_t)s.batch.size();
+    S->inflight -= (int64_t)s.batch.size();
+    S->t_last = now;
+    s.batch.clear();
+    s.busy = false;
+    S->cv_done.notify_all();
+}
+
+void worker_loop(jag_server *S)
+{
+    (void)hipSetDevice(S->idx->ix.device);
+    const auto max_wait = std::chrono::microseconds(S->P.max_wait_us);
+    for (;;) {
+        bool progressed = false;
+        // 1. retire finished batches
+        for (auto &s : S->slots) {
+            if (s.busy && hipEventQuery(s.event) == hipSuccess) {
+                finish(S, s);
+                progressed = true;
+            }
+        }
+        // 2. admit pending requests onto idle streams
+        for (auto &s : S->slots) {
+            if (s.busy) continue;
+            {
+                std::unique_lock<std::mutex> lk(S->mu);
+                if (S->pending.empty()) break;
+                int64_t room = S->max_inflight - S->inflight;
+                if (room <= 0) break;
+                int64_t want = std::min<int64_t>({(int64_t)S->P.max_batch, room, (int64_t)S->pending.size()});
+                // a partial batch waits briefly for company while other batches run
+                bool others = S->inflight > 0;
+                if (want < S->P.max_batch && others &&
+                    clk::now() - S->pending.front().t_submit < max_wait)
+                    break;
+                for (int64_t i = 0; i < want; i++) {
+                    s.batch.push_back(std::move(S->pending.front()));
+                    S->pending.pop_front();
+                }
+                S->inflight += want;
+                S->max_inflight_seen = std::max(S->max_inflight_seen, S->inflight);
+                S->batches++;
+                S->batched_requests += want;
+                s.busy = true;
+            }
+            if (!launch(S, s)) {
+                std::lock_guard<std::mutex> g(S->mu);
+                S->error = jag_last_error();
+                S->stop = true;
+                S->cv_done.notify_all();
+                return;
+            }
+            progressed = true;
+        }
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            bool busy = false;
+            for (auto &s : S->slots) busy |= s.busy;
+            if (S->stop && S->pending.empty() && !busy) return;
+            if (!progressed) {
+                if (!busy && S->pending.empty())
+                    S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                else {
+                    lk.unlock();
+                    std::this_thread::sleep_for(std::chrono::microseconds(20));
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_server **out)
+{
+    using jag::set_error;
+    if (!idx || !P || !out) {
+        set_error("null argument");
+        return JAG_EINVAL;
+    }
+    *out = nullptr;
+    if (P->k < 1 || P->k > 64 || P->max_batch < 1 || P->max_batch > 4096 || P->n_streams < 1 ||
+        P->n_streams > 8 || P->max_wait_us < 0 || P->max_inflight < 0 || P->queue_capacity < 1 ||
+        P->search.stats || P->search.features || P->search.learned == 2) {
+        set_error("bad server parameters");
+        return JAG_EINVAL;
+    }
+    jag::Index &ix = idx->ix;
+    if (hipSetDevice(ix.device) != hipSuccess) {
+        set_error("cannot select device %d", ix.device);
+        return JAG_EDEVICE;
+    }
+    int64_t resident = 0;
+    size_t lds = 0;
+    jag_status st = jag::search_capacity(ix, P->k, P->search, &resident, &lds);
+    if (st != JAG_OK) return st;
+    int64_t dev_bytes = (int64_t)P->n_streams * slot_device_bytes(P->max_batch, ix.d, P->k);
+    if (P->hbm_budget_bytes > 0 && dev_bytes > P->hbm_budget_bytes) {
+        set_error("server buffers need %lld bytes, over the %lld-byte budget", (long long)dev_bytes,
+                  (long long)P->hbm_budget_bytes);
+        return JAG_EUNSUPPORTED;
+    }
+    auto *S = new (std::nothrow) jag_server;
+    if (!S) return JAG_ENOMEM;
+    S->idx = idx;
+    S->P = *P;
+    S->resident = resident;
+    S->max_inflight = P->max_inflight > 0 ? P->max_inflight : std::max<int64_t>(resident, P->max_batch);
+    S->device_bytes = dev_bytes;
+    S->slots.resize(P->n_streams);
+    for (auto &s : S->slots) {
+        if (!alloc_slot(s, P->max_batch, ix.d, P->k)) {
+            for (auto &x : S->slots) free_slot(x);
+            delete S;
+            set_error("server buffer allocation failed");
+            return JAG_ENOMEM;
+        }
+    }
+    S->worker = std::thread(worker_loop, S);
+    *out = S;
+    return JAG_OK;
+}
+
+jag_status jag_server_submit(jag_server *S, const float *Q, const jag_filter *F, int64_t n,
+                             const int32_t *pool, int64_t pool_len, uint64_t *tickets_out)
+{
+    using jag::set_error;
+    if (!S || n < 0 || (n > 0 && (!Q || !F || !tickets_out))) {
+        set_error("null argument");
+        return JAG_EINVAL;
+    }
+    if (n == 0) return JAG_OK;
+    const int d = S->idx->ix.d;
+    std::vector<jag::FilterRecord> rec(n);
+    jag_status st = jag::encode_filters(S->idx->ix, F, n, pool, pool_len, rec.data());
+    if (st != JAG_OK) return st;
+    for (int64_t i = 0; i < n * d; i++)
+        if (!std::isfinite(Q[i])) {
+            set_error("query element %lld is not finite", (long long)i);
+            return JAG_EINVAL;
+        }
+    auto now = clk::now();
+    std::lock_guard<std::mutex> g(S->mu);
+    if (!S->error.empty()) {
+        set_error("server stopped after an error: %s", S->error.c_str());
+        return JAG_EDEVICE;
+    }
+    if ((int64_t)S->pending.size() + n > S->P.queue_capacity) {
+        set_error("queue full (%lld pending)", (long long)S->pending.size());
+        return JAG_EBUSY;
+    }
+    if (!S->have_first) {
+        S->t_first = now;
+        S->have_first = true;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        Request r;
+        r.ticket = S->next_ticket++;
+        r.rec = rec[i];
+        r.q.assign(Q + i * d, Q + (i + 1) * d);
+        r.t_submit = now;
+        tickets_out[i] = r.ticket;
+        S->pending.push_back(std::move(r));
+    }
+    S->submitted += n;
+    S->cv_work.notify_one();
+    return JAG_OK;
+}
+
+jag_status jag_server_poll(jag_server *S, uint64_t ticket, int32_t *ids, float *dists, int32_t *count,
+                           double *latency_us)
+{
+    using jag::set_error;
+    if (!S || !ids || !dists || !count) {
+        set_error("null argument");
+        return JAG_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->done.find(ticket);
+    if (it == S->done.end()) {
+        if (ticket == 0 || ticket >= S->next_ticket) {
+            set_error("unknown ticket %llu", (unsigned long long)ticket);
+            return JAG_EINVAL;
+        }
+        if (!S->error.empty()) {
+            set_error("server stopped after an error: %s", S->error.c_str());
+            return JAG_EDEVICE;
+        }
+        return JAG_EAGAIN;
+    }
+    std::copy(it->second.ids.begin(), it->second.ids.end(), ids);
+    std::copy(it->second.dists.begin(), it->second.dists.end(), dists);
+    *count = it->second.count;
+    if (latency_us) *latency_us = it->second.latency_us;
+    S->done.erase(it);
+    return JAG_OK;
+}
+
+jag_status jag_server_drain(jag_server *S)
+{
+    if (!S) {
+        jag::set_error("null argument");
+        return JAG_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->completed == S->submitted || !S->error.empty(); });
+    if (!S->error.empty()) {
+        jag::set_error("server stopped after an error: %s", S->error.c_str());
+        return JAG_EDEVICE;
+    }
+    return JAG_OK;
+}
+
+jag_status jag_server_stats_get(jag_server *S, jag_server_stats *o)
+{
+    if (!S || !o) {
+        jag::set_error("null argument");
+        return JAG_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    std::memset(o, 0, sizeof(*o));
+    o->submitted = S->submitted;
+    o->completed = S->completed;
+    o->batches = S->batches;
+    o->max_inflight_seen = S->max_inflight_seen;
+    o->resident_capacity = S->resident;
+    o->device_bytes = S->device_bytes;
+    o->mean_batch = S->batches ? (double)S->batched_requests / (double)S->batches : 0.0;
+    if (!S->latencies.empty()) {
+        std::vector<double> v = S->latencies;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            size_t i = (size_t)std::ceil(p * (double)v.size()) - 1;
+            return v[std::min(i, v.size() - 1)];
+        };
+        o->p50_us = pct(0.50);
+        o->p99_us = pct(0.99);
+        o->max_us = v.back();
+        double s = 0;
+        for (double x : v) s += x;
+        o->mean_us = s / (double)v.size();
+        double span = std::chrono::duration<double>(S->t_last - S->t_first).count();
+        o->qps = span > 0 ? (double)S->completed / span : 0.0;
+    }
+    return JAG_OK;
+}
+
+void jag_server_stop(jag_server *S)
+{
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->stop = true;
+        S->cv_work.notify_all();
+    }
+    if (S->worker.joinable()) S->worker.join();
+    for (auto &s : S->slots) {
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+        free_slot(s);
+    }
+    delete S;
+}
+
+}  // extern "C"

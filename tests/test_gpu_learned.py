@@ -96,7 +96,8 @@ def test_learned_search_matches_oracle(c1_small):
         assert same.mean() >= 0.7
         assert np.array_equal(g["ids"][same], orc.ids[same])
         assert np.array_equal(g["stats"][same, 0], orc.hops[same])
-        _say(f"delta={delta} compared {same.sum()} queries exactly; beams {np.bincount(lh)[ladder]}")
+        _say(f"delta={delta} compared {same.sum()} queries exactly; "
+             f"beams {np.bincount(lh, minlength=int(ladder[-1]) + 1)[ladder]}")
 
 
 def test_learned_cut_is_exact(c1_small):
