@@ -104,7 +104,9 @@ def exported_symbols() -> list[str]:
     return ["jag_build", "jag_build_graph", "jag_build_from_graph", "jag_save", "jag_load", "jag_free", "jag_info",
             "jag_get_graph", "jag_get_store", "jag_encode_filters", "jag_search_encoded",
             "jag_search_batch", "jag_exact_knn", "jag_set_predictor", "jag_train_predictor",
-            "jag_predictor_grad", "jag_last_error", "jag_version"]
+            "jag_predictor_grad", "jag_last_error", "jag_version", "jag_server_start",
+            "jag_server_submit", "jag_server_poll", "jag_server_drain", "jag_server_stats_get",
+            "jag_server_stop"]
 
 
 def _check(st: int):
@@ -319,3 +321,108 @@ def jag_predictor_grad(features, targets, params, stream=None):
     _check(lib().jag_predictor_grad(_ptr(features), _ptr(targets), features.shape[0], _ptr(p),
                                     _ptr(loss), _ptr(g), _stream(stream)))
     return float(loss[0]), g
+
+
+# ---------------------------------------------------------------- serving
+
+class jag_server_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("search", jag_search_params), ("max_batch", C.c_int32),
+                ("n_streams", C.c_int32), ("max_wait_us", C.c_int32), ("max_inflight", C.c_int64),
+                ("queue_capacity", C.c_int64), ("hbm_budget_bytes", C.c_int64)]
+
+
+class jag_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("max_inflight_seen", C.c_int64), ("resident_capacity", C.c_int64),
+                ("p50_us", C.c_double), ("p99_us", C.c_double), ("mean_us", C.c_double),
+                ("max_us", C.c_double), ("qps", C.c_double), ("mean_batch", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+
+JAG_EBUSY, JAG_EAGAIN = -6, 1
+_SERVER_SIG = {
+    "jag_server_start": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "jag_server_submit": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                           C.c_void_p], C.c_int32),
+    "jag_server_poll": ([C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                        C.c_int32),
+    "jag_server_drain": ([C.c_void_p], C.c_int32),
+    "jag_server_stats_get": ([C.c_void_p, C.c_void_p], C.c_int32),
+    "jag_server_stop": ([C.c_void_p], None),
+}
+
+
+def _server_lib():
+    L = lib()
+    if not getattr(L, "_server_sig_set", False):
+        for name, (args, res) in _SERVER_SIG.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        L._server_sig_set = True
+    return L
+
+
+class Server:
+    """Owning handle of a jag_server (keeps its index alive)."""
+
+    def __init__(self, handle, idx: Index, k: int):
+        self._h, self.idx, self.k = handle, idx, k
+
+    def stop(self):
+        if self._h:
+            _server_lib().jag_server_stop(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def jag_server_start(idx: Index, k: int, search: SearchParams, max_batch: int = 1024,
+                     n_streams: int = 4, max_wait_us: int = 200, max_inflight: int = 0,
+                     queue_capacity: int = 1 << 22, hbm_budget_bytes: int = 0) -> Server:
+    p = jag_server_params(int(k), search.c(), int(max_batch), int(n_streams), int(max_wait_us),
+                          int(max_inflight), int(queue_capacity), int(hbm_budget_bytes))
+    h = C.c_void_p()
+    _check(_server_lib().jag_server_start(idx.handle, C.byref(p), C.byref(h)))
+    return Server(h, idx, k)
+
+
+def jag_server_submit(s: Server, Q, F, pool) -> np.ndarray:
+    Q = _np(Q, np.float32)
+    F = _np(F, np.int32)
+    pool = _np(pool, np.int32)
+    n = F.shape[0]
+    t = np.empty(n, dtype=np.uint64)
+    _check(_server_lib().jag_server_submit(s._h, _ptr(Q), _ptr(F), n, _ptr(pool), pool.size, _ptr(t)))
+    return t
+
+
+def jag_server_poll(s: Server, ticket: int):
+    """(ids, dists, count, latency_us) when done, None while pending."""
+    ids = np.empty(s.k, dtype=np.int32)
+    d = np.empty(s.k, dtype=np.float32)
+    c = C.c_int32()
+    lat = C.c_double()
+    st = _server_lib().jag_server_poll(s._h, int(ticket), _ptr(ids), _ptr(d), C.byref(c), C.byref(lat))
+    if st == JAG_EAGAIN:
+        return None
+    _check(st)
+    return ids, d, int(c.value), float(lat.value)
+
+
+def jag_server_drain(s: Server):
+    _check(_server_lib().jag_server_drain(s._h))
+
+
+def jag_server_stats_get(s: Server) -> dict:
+    o = jag_server_stats()
+    _check(_server_lib().jag_server_stats_get(s._h, C.byref(o)))
+    return {f: getattr(o, f) for f, _ in jag_server_stats._fields_}
+
+
+def jag_server_stop(s: Server):
+    s.stop()
