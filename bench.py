@@ -53,6 +53,8 @@ def parse():
                     help="run only the operating point (for rocprofv3); needs --L and --store")
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
+    ap.add_argument("--calib-bytes", type=int, default=0,
+                    help="profile mode: also run device copies of this many bytes")
     ap.add_argument("--graph-cache", default=None,
                     help="load the graph from this .npz if present, else build and save it there")
     return ap.parse_args()
@@ -140,6 +142,14 @@ def main():
             jag.jag_search_encoded(ix32, Qd, rec32, k, sp, ids, d2, cnt)
         torch.cuda.synchronize()
         log(f"profiled {args.steps} steps of fp32 L={args.L}")
+        if args.calib_bytes:
+            # a plain device copy of known size, to scale the memory counters
+            src = torch.empty(args.calib_bytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"calibration copies of {args.calib_bytes} bytes done")
         return
 
     # ---- ground truth: the oracle's exact filtered k-NN in FP64

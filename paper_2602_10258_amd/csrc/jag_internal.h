@@ -68,7 +68,8 @@ struct Index {
     std::vector<int64_t> label_count;
     // device memory
     int device = 0;
-    int32_t *d_adj = nullptr;
+    int32_t *d_adj = nullptr;  // rows of adj_words: ids, then the neighbours' attribute words
+    int32_t adj_words = 0, scal_word_off = 0, lab_word_off = 0;
     unsigned char *d_vec = nullptr;  // search store rows, vec_stride bytes each
     int32_t vec_stride = 0;
     unsigned char *d_f32 = nullptr;  // FP32 rows (== d_vec for an FP32 store), f32_stride bytes

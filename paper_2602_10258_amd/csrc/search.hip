@@ -50,6 +50,7 @@ struct SearchArgs {
     float *features;
     const uint16_t *pred;
     int32_t vec_stride, f32_stride, W, d, R, entry;
+    int32_t adj_words, scal_word_off, lab_word_off;  // adjacency row layout (words)
     int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder;
     float delta, rho;
     int32_t ladder[JAG_LADDER_MAX];
@@ -72,17 +73,16 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 // Section 3.1: label -> [label missing]; range -> distance to [lo, hi];
 // subset -> number of required labels missing; Boolean DNF -> fewest
 // literals to flip in the cheapest satisfiable clause.
-__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, int32_t u, const SearchArgs &a)
-{
-    if (f.type == F_RANGE) {
-        int64_t v = a.scalar[u];
-        if (v < f.a) return (uint32_t)((int64_t)f.a - v);
-        if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
-        return 0u;
-    }
+// The attribute words of one item as the filter needs them: the scalar for
+// a range filter, else the label row (two uint16 labels per word, 0xFFFF
+// padded).
+struct ItemAttr {
+    int32_t scalar;
     uint32_t w[8];
-    const unsigned char *row = reinterpret_cast<const unsigned char *>(a.lab) + (int64_t)u * a.W * 2;
-    int nw = a.W >> 1;
+};
+
+__device__ __forceinline__ void load_label_words(uint32_t *w, const unsigned char *row, int nw)
+{
     if (nw == 1) {
         w[0] = *reinterpret_cast<const uint32_t *>(row);
     } else if (nw == 2) {
@@ -103,6 +103,42 @@ __device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, int32_t u, con
             w[7] = s.w;
         }
     }
+}
+
+// from the per-item attribute arrays
+__device__ __forceinline__ void load_item_attr(ItemAttr &at, const FilterRecord &f, int32_t u,
+                                               const SearchArgs &a)
+{
+    if (f.type == F_RANGE) {
+        at.scalar = a.scalar[u];
+        return;
+    }
+    load_label_words(at.w, reinterpret_cast<const unsigned char *>(a.lab) + (int64_t)u * a.W * 2, a.W >> 1);
+}
+
+// from the adjacency row of the vertex being expanded: the row carries, after
+// the R neighbour ids, each neighbour's scalar and label words (slot j)
+__device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &f, const int32_t *row,
+                                              int j, const SearchArgs &a)
+{
+    if (f.type == F_RANGE) {
+        at.scalar = row[a.scal_word_off + j];
+        return;
+    }
+    load_label_words(at.w, reinterpret_cast<const unsigned char *>(row + a.lab_word_off) + j * a.W * 2,
+                     a.W >> 1);
+}
+
+__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr &at, const SearchArgs &a)
+{
+    if (f.type == F_RANGE) {
+        int64_t v = at.scalar;
+        if (v < f.a) return (uint32_t)((int64_t)f.a - v);
+        if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
+        return 0u;
+    }
+    const uint32_t *w = at.w;
+    int nw = a.W >> 1;
     // static loop bounds keep the (uniform) record in scalar registers
     uint32_t present = 0;
 #pragma unroll
@@ -471,7 +507,9 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
     // L <- {s}
     if (lane == 0) {
         s.cid[0] = a.entry;
-        s.cdf[0] = dist_f(f, a.entry, a);
+        ItemAttr at;
+        load_item_attr(at, f, a.entry, a);
+        s.cdf[0] = dist_f(f, at, a);
     }
     __syncthreads();
     eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, 1, qr);
@@ -499,9 +537,17 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
             if (hops < 4) s.exkey[hops] = s.key[hint];
         }
         hops++;
-        int32_t u = lane < a.R ? a.adj[(int64_t)p * a.R + lane] : -1;
+        // one row holds the neighbour ids and their attribute words: both
+        // loads are issued together, before the ids are known
+        const int32_t *row = a.adj + (int64_t)p * a.adj_words;
+        int32_t u = -1;
+        ItemAttr at;
+        if (lane < a.R) {
+            u = row[lane];
+            load_row_attr(at, f, row, lane, a);
+        }
         bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
-        uint32_t df = fresh ? dist_f(f, u, a) : 0u;
+        uint32_t df = fresh ? dist_f(f, at, a) : 0u;
         nattr += __popcll(ballot64(fresh));
         if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
         uint64_t bm = ballot64(fresh);
@@ -641,7 +687,12 @@ __global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
     for (int64_t i0 = 0; i0 < n; i0 += 64) {
         int64_t i = i0 + lane;
         bool ok = i < n;
-        uint32_t df = ok ? dist_f(f, (int32_t)i, a) : 1u;
+        uint32_t df = 1u;
+        if (ok) {
+            ItemAttr at;
+            load_item_attr(at, f, (int32_t)i, a);
+            df = dist_f(f, at, a);
+        }
         ok = ok && df == 0;
         uint64_t bm = ballot64(ok);
         int m = __popcll(bm);
@@ -800,10 +851,12 @@ ExactFn exact_for_ch(int ch)
     return nullptr;
 }
 
-int hash_size_for(int Lcap)
+// Measured on the range workload (L = 48): 2^11 slots beat 2^10 (fewer
+// repeated evaluations) and 2^12 (lower occupancy).
+int hash_size_for(int L)
 {
-    int h = 1024;
-    while (h < 16 * Lcap && h < 8192) h <<= 1;
+    int h = 2048;
+    while (h < 24 * L && h < 4096) h <<= 1;
     return h;
 }
 
@@ -821,8 +874,42 @@ jag_status upload_index(Index &ix)
     const int64_t n = ix.n;
     const int d = ix.d;
     jag_status st;
-    if ((st = dalloc(&ix.d_adj, sizeof(int32_t) * n * ix.R, ix.device_bytes)) != JAG_OK) return st;
-    HIPCHK(hipMemcpy(ix.d_adj, ix.adj.data(), sizeof(int32_t) * n * ix.R, hipMemcpyHostToDevice));
+    // adjacency rows with the neighbours' attributes inlined:
+    //   [R ids][R scalars, if any][R x W/2 label words, if any], each part
+    //   starting on a 16-byte boundary; -1 / 0 / 0xFFFF padding
+    auto up4 = [](int x) { return (x + 3) / 4 * 4; };
+    ix.scal_word_off = ix.has_scalar ? up4(ix.R) : 0;
+    ix.lab_word_off = ix.has_labels ? up4(ix.has_scalar ? ix.scal_word_off + ix.R : ix.R) : 0;
+    ix.adj_words = up4(ix.has_labels ? ix.lab_word_off + ix.R * (ix.W / 2)
+                                     : (ix.has_scalar ? ix.scal_word_off + ix.R : ix.R));
+    if ((st = dalloc(&ix.d_adj, sizeof(int32_t) * n * ix.adj_words, ix.device_bytes)) != JAG_OK) return st;
+    {
+        const int64_t chunk = 1 << 16;
+        std::vector<int32_t> buf((size_t)std::min<int64_t>(chunk, n) * ix.adj_words);
+        for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+            int64_t r1 = std::min<int64_t>(n, r0 + chunk);
+            std::fill(buf.begin(), buf.end(), 0);
+            for (int64_t i = r0; i < r1; i++) {
+                int32_t *o = buf.data() + (size_t)(i - r0) * ix.adj_words;
+                const int32_t *nb = ix.adj.data() + (size_t)i * ix.R;
+                uint16_t *lw = reinterpret_cast<uint16_t *>(o + ix.lab_word_off);
+                for (int j = 0; j < ix.R; j++) {
+                    int32_t v = nb[j];
+                    o[j] = v;
+                    if (ix.has_scalar) o[ix.scal_word_off + j] = v >= 0 ? ix.scalar[v] : 0;
+                    if (ix.has_labels) {
+                        uint16_t *dst = lw + (size_t)j * ix.W;
+                        for (int t = 0; t < ix.W; t++) dst[t] = 0xFFFF;
+                        if (v >= 0)
+                            for (int64_t x = ix.loff[v]; x < ix.loff[v + 1]; x++)
+                                dst[x - ix.loff[v]] = (uint16_t)ix.lab[x];
+                    }
+                }
+            }
+            HIPCHK(hipMemcpy(ix.d_adj + r0 * ix.adj_words, buf.data(),
+                             sizeof(int32_t) * (r1 - r0) * ix.adj_words, hipMemcpyHostToDevice));
+        }
+    }
     if (ix.has_scalar) {
         if ((st = dalloc(&ix.d_scalar, sizeof(int32_t) * n, ix.device_bytes)) != JAG_OK) return st;
         HIPCHK(hipMemcpy(ix.d_scalar, ix.scalar.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
@@ -963,6 +1050,9 @@ static jag_status fill_args(Index &ix, SearchArgs &a, const float *Q, const void
     a.W = ix.W;
     a.d = ix.d;
     a.R = ix.R;
+    a.adj_words = ix.adj_words;
+    a.scal_word_off = ix.scal_word_off;
+    a.lab_word_off = ix.lab_word_off;
     a.entry = ix.entry;
     a.k = k;
     return JAG_OK;

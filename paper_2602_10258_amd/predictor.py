@@ -115,8 +115,14 @@ def fit(idx, Q, F, pool, k: int = 10, epochs: int = 40, batch: int = 512, lr: fl
     feats, all_ids, hops = traces(idx, Qd, rec, k, ladder, rerank_mult)
     tgt, reached = targets_from(all_ids, exact_ids, exact_cnt, k)
     if dump:
+        nl, nq = all_ids.shape[0], all_ids.shape[1]
+        hits = np.zeros((nl, nq), dtype=np.int8)
+        for q in range(nq):
+            gt = set(exact_ids[q, :min(k, int(exact_cnt[q]))].tolist())
+            for i in range(nl):
+                hits[i, q] = len(gt.intersection(all_ids[i, q].tolist()))
         np.savez_compressed(dump, features=feats, targets=tgt, reached=reached, hops=hops,
-                            ladder=ladder)
+                            ladder=ladder, hits=hits, exact_cnt=exact_cnt)
     ok = feats[:, 15] == 1.0  # rows with four expansions
     X = torch.from_numpy(np.ascontiguousarray(feats[ok])).cuda()
     T = torch.from_numpy(tgt[ok].astype(np.float32)).cuda()
