@@ -52,7 +52,12 @@ def parse():
     ap.add_argument("--profile-op", action="store_true",
                     help="run only the operating point (for rocprofv3); needs --L and --store")
     ap.add_argument("--L", type=int, default=48)
+    ap.add_argument("--op-mode", default="fp32-fixed",
+                    choices=["fp32-fixed", "bf16+rerank-fixed", "learned+bf16+rerank"])
+    ap.add_argument("--delta", type=float, default=0.0)
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson arrivals)")
+    ap.add_argument("--rates", default="5000,20000,50000,100000,200000")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="profile mode: also run device copies of this many bytes")
     ap.add_argument("--graph-cache", default=None,
@@ -87,7 +92,126 @@ THRESHOLDS = {
     "c1": [(1, 1.0), (1, 0.0)],
     "c2": [(0, 1.0), (0, 0.01), (0, 0.0)],
     "c3": [(1, 1.0), (1, 0.01), (1, 0.0)],
+    "c5": [(0, 1.0), (0, 0.01), (0, 0.0), (1, 0.01), (1, 0.0)],
 }
+
+
+def measured_traffic(workload: str, op_name: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, only if it was taken on this exact kernel source and operating
+    point; otherwise None."""
+    import hashlib
+    p = os.path.join(ROOT, "profiles", f"search_kernel_{workload}_counters.json")
+    src = os.path.join(ROOT, "paper_2602_10258_amd", "csrc", "search.hip")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    if d.get("search_hip_sha1") != sha or d.get("operating_point") != op_name:
+        return None
+    return d["traffic_bytes_per_launch"]
+
+
+def serve_main(args):
+    """Serving: Poisson arrivals of mixed Label/Range/Subset/Boolean queries on
+    one GPU's shard of the 10M-vector serving workload (FP8 store + FP32
+    rerank, learned beam).  Prints one JSON line with p50/p99 latency and the
+    achieved QPS per offered rate."""
+    import torch
+    from oracle import oracle as O
+    from paper_2602_10258_amd import jag
+    from paper_2602_10258_amd import predictor as pred
+    from workloads import make_config
+    from workloads.gen import extra_queries, poisson_arrivals
+
+    n = args.n or 1_250_000
+    w = make_config("c5", n=n, nq=args.nq or 10000)
+    k = w.k
+    log(f"serving workload c5 shard: n={w.n} d={w.d} nq={w.nq}")
+    t1 = time.time()
+    if args.graph_cache and os.path.exists(args.graph_cache):
+        z = np.load(args.graph_cache)
+        adj, entry = z["adj"], int(z["entry"])
+    else:
+        adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
+                                         vocab=w.vocab, R=w.R, L_build=2 * w.R,
+                                         thresholds=THRESHOLDS["c5"], seed=0)
+        if args.graph_cache:
+            np.savez(args.graph_cache, adj=adj, entry=entry)
+    log(f"graph ready in {time.time() - t1:.1f}s")
+    kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
+    ix = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_FP8_E4M3, keep_f32=True, **kw)
+    Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
+    _, rho, rep = pred.fit(ix, Qt, Ft, pt, k=k, rerank_mult=4)
+    log(f"predictor: loss {rep.loss_first:.2f} -> {rep.loss_last:.2f}, rho {rho:.2f}")
+    nthr = min(os.cpu_count() or 1, 16)
+    A = O.attrs_of(w)
+    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, k, nthreads=nthr)
+
+    def recall_of(ids_np):
+        r = []
+        for q in range(len(ids_np)):
+            den = min(k, int(nv[q]))
+            if den:
+                r.append(len(set(gi[q, :den].tolist()) & set(ids_np[q].tolist())) / den)
+        return float(np.mean(r))
+
+    # the smallest offset reaching recall 0.95 on the batch path
+    dev = torch.device("cuda:0")
+    rec = torch.from_numpy(jag.jag_encode_filters(ix, w.F, w.pool)).to(dev)
+    Qd = torch.from_numpy(w.Q).to(dev)
+    ids = torch.empty((w.nq, k), dtype=torch.int32, device=dev)
+    dd = torch.empty((w.nq, k), dtype=torch.float32, device=dev)
+    cnt = torch.empty((w.nq,), dtype=torch.int32, device=dev)
+    delta = None
+    for dl in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]:
+        sp = jag.SearchParams(L=k, learned=1, delta=dl, rerank_mult=4)
+        jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, dd, cnt)
+        torch.cuda.synchronize()
+        r = recall_of(ids.cpu().numpy())
+        log(f"delta {dl:+.1f}: batch recall {r:.4f}")
+        if r >= 0.95:
+            delta = dl
+            break
+    if delta is None:
+        delta = 6.0
+    sp = jag.SearchParams(L=k, learned=1, delta=delta, rerank_mult=4)
+    rates = [float(x) for x in args.rates.split(",")]
+    per_rate = []
+    for qps in rates:
+        m = min(w.nq, max(2000, int(qps * 1.0)))
+        arr = poisson_arrivals(np.random.default_rng(int(qps)), m, qps)
+        s = jag.jag_server_start(ix, k, sp, max_batch=4096, n_streams=4, max_wait_us=100)
+        t0 = time.perf_counter()
+        tick = np.empty(m, dtype=np.uint64)
+        i = 0
+        while i < m:
+            now = time.perf_counter() - t0
+            j = int(np.searchsorted(arr, now, side="right"))
+            if j > i:
+                tick[i:j] = jag.jag_server_submit(s, w.Q[i:j], w.F[i:j], w.pool)
+                i = j
+            else:
+                time.sleep(max(0.0, min(1e-4, arr[i] - now)))
+        jag.jag_server_drain(s)
+        st = jag.jag_server_stats_get(s)
+        got = np.empty((m, k), dtype=np.int32)
+        for q in range(m):
+            got[q] = jag.jag_server_poll(s, int(tick[q]))[0]
+        jag.jag_server_stop(s)
+        r = recall_of(got)
+        row = {"offered_qps": qps, "requests": m, "achieved_qps": round(st["qps"], 1),
+               "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+               "mean_batch": round(st["mean_batch"], 1), "max_inflight": st["max_inflight_seen"],
+               "resident_capacity": st["resident_capacity"], "recall_at_10": round(r, 4)}
+        log(row)
+        per_rate.append(row)
+    out = {"metric": "serving latency (p50/p99) and QPS, mixed filters, learned beam + FP8 + FP32 rerank",
+           "config": {"workload": f"c5 shard: {w.n} x {w.d} (10M / 8), FP8 E4M3 + per-row scale, "
+                                  f"R={w.R}, mixed Label/Range/Subset/Boolean, Poisson arrivals",
+                      "delta": delta, "rho": rho},
+           "rates": per_rate}
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -96,6 +220,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described in DESIGN.md and not built.", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        return serve_main(args)
     import torch
     from paper_2602_10258_amd import jag
     from paper_2602_10258_amd import predictor as pred
@@ -137,11 +263,18 @@ def main():
 
     if args.profile_op:
         # only the operating point, for rocprofv3 (no sweeps, no ground truth)
-        sp = jag.SearchParams(L=args.L)
+        if args.op_mode == "fp32-fixed":
+            ix, rec, sp = ix32, rec32, jag.SearchParams(L=args.L)
+        elif args.op_mode == "bf16+rerank-fixed":
+            ix, rec, sp = ix16, rec16, jag.SearchParams(L=args.L, rerank_mult=4)
+        else:
+            Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
+            pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4)
+            ix, rec, sp = ix16, rec16, jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4)
         for i in range(args.warmup + args.steps):
-            jag.jag_search_encoded(ix32, Qd, rec32, k, sp, ids, d2, cnt)
+            jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, d2, cnt)
         torch.cuda.synchronize()
-        log(f"profiled {args.steps} steps of fp32 L={args.L}")
+        log(f"profiled {args.steps} steps of {args.op_mode} L={args.L}")
         if args.calib_bytes:
             # a plain device copy of known size, to scale the memory counters
             src = torch.empty(args.calib_bytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -184,13 +317,23 @@ def main():
                     nattr=float(st[:, 2].mean()), lhat=float(st[:, 3].mean()))
 
     # ---- plain FP32, fixed beam sweep
+    ladder_fixed = [10, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 56, 64, 80, 96, 128, 192, 256]
     fixed = []
-    for L in [10, 12, 16, 20, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]:
+    for L in ladder_fixed:
         r = point(ix32, rec32, jag.SearchParams(L=L))
         r["L"] = L
         fixed.append(r)
         log(f"fp32 L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f} hops={r['hops']:.1f}")
-        if r["recall"] >= 0.995:
+        if r["recall"] >= 0.99:
+            break
+    # ---- ablation: BF16 + FP32 rerank with a fixed beam (no predictor)
+    fixed16 = []
+    for L in ladder_fixed:
+        r = point(ix16, rec16, jag.SearchParams(L=L, rerank_mult=4))
+        r["L"] = L
+        fixed16.append(r)
+        log(f"bf16+rerank L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
+        if r["recall"] >= 0.99:
             break
 
     # ---- learned + BF16 + FP32 rerank
@@ -225,16 +368,23 @@ def main():
         return best, interp
 
     best_f, interp_f = at95(fixed)
+    best_f16, interp_f16 = at95(fixed16)
     best_l, interp_l = at95(learned) if learned else (None, None)
-    use_learned = best_l is not None and (best_f is None or best_l["qps"] >= best_f["qps"])
-    if use_learned:
-        op = dict(mode="learned+bf16+rerank", ix=ix16, rec=rec16,
-                  sp=jag.SearchParams(L=k, learned=1, delta=best_l["delta"], rerank_mult=4),
-                  store=jag.STORE_BF16, rerank=True, point=best_l)
-    else:
-        assert best_f is not None, "no fixed beam reached recall 0.95"
-        op = dict(mode="fp32-fixed", ix=ix32, rec=rec32, sp=jag.SearchParams(L=best_f["L"]),
-                  store=jag.STORE_F32, rerank=False, point=best_f)
+    cands = []
+    if best_l:
+        cands.append(dict(mode="learned+bf16+rerank", ix=ix16, rec=rec16,
+                          sp=jag.SearchParams(L=k, learned=1, delta=best_l["delta"], rerank_mult=4),
+                          store=jag.STORE_BF16, rerank=True, point=best_l))
+    if best_f16:
+        cands.append(dict(mode="bf16+rerank-fixed", ix=ix16, rec=rec16,
+                          sp=jag.SearchParams(L=best_f16["L"], rerank_mult=4),
+                          store=jag.STORE_BF16, rerank=True, point=best_f16))
+    if best_f:
+        cands.append(dict(mode="fp32-fixed", ix=ix32, rec=rec32, sp=jag.SearchParams(L=best_f["L"]),
+                          store=jag.STORE_F32, rerank=False, point=best_f))
+    assert cands, "no configuration reached recall 0.95"
+    op = max(cands, key=lambda c: c["point"]["qps"])
+    log(f"operating point: {op['mode']} ({op['point']})")
 
     # ---- timed steps
     def step():
@@ -270,6 +420,8 @@ def main():
         per_q = per_q + 4 * k * 4 * w.d
     alg_bytes = float(per_q.sum())
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
+    op_name = f"{op['mode']} L={op['sp'].L}" if not op["sp"].learned else op["mode"]
+    traffic = measured_traffic(w.name, op_name)
 
     # ---- CPU baseline: the oracle, unchanged, on a bounded sample at the same beam
     cpu = None
@@ -293,7 +445,8 @@ def main():
                    "global_batch": nq, "mode": op["mode"], "recall_at_10": round(rec_final, 4),
                    "storage": "bf16 (+fp32 rerank)" if op["rerank"] else "fp32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
+        "operating_point": op_name,
         "cpu_baseline": cpu,
         "qps_at_095": {
             "learned_bf16_measured": best_l and round(best_l["qps"], 1),
@@ -301,6 +454,9 @@ def main():
             "fp32_fixed_measured": best_f and round(best_f["qps"], 1),
             "fp32_fixed_interp": interp_f and round(interp_f, 1),
             "fp32_fixed_L": best_f and best_f["L"],
+            "bf16_rerank_fixed_measured": best_f16 and round(best_f16["qps"], 1),
+            "bf16_rerank_fixed_interp": interp_f16 and round(interp_f16, 1),
+            "bf16_rerank_fixed_L": best_f16 and best_f16["L"],
         },
         "kernel_ms": round(kern_ms, 4),
         "alg_bytes_per_query": round(alg_bytes / nq, 1),
@@ -309,6 +465,8 @@ def main():
         "build_seconds": round(build_s, 1),
         "sweeps": {"fixed": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
                              for r in fixed],
+                   "bf16_rerank_fixed": [{k_: (round(v, 4) if isinstance(v, float) else v)
+                                          for k_, v in r.items()} for r in fixed16],
                    "learned": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
                                for r in learned]},
         "predictor": fit_rep and fit_rep.__dict__,

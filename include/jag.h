@@ -123,7 +123,12 @@ typedef struct {
 typedef struct {
     int32_t L;           /* beam width l_s (fixed mode), k..1024 */
     int32_t learned;     /* 0 = fixed beam L; 1 = predicted beam (index needs a predictor);
-                            2 = fixed beam L plus predictor features written to `features` */
+                            2 = fixed beam L plus predictor features written to `features`.
+                            In modes 1 and 2 the first four expansions keep a list of
+                            max(128, widest beam) entries (mode 1: the ladder's last
+                            entry, mode 2: L); the features are taken after the fourth
+                            expansion and the list is then cut to the beam, which gives
+                            exactly the fixed-beam search's state */
     float delta;         /* learned mode: offset added to the predicted ladder index */
     int32_t rerank_mult; /* 0 = none; m > 0 rescores the best m*k entries of the final list
                             from the FP32 copy (needs keep_f32 or an FP32 store); m*k <= 64 */

@@ -51,7 +51,7 @@ struct SearchArgs {
     const uint16_t *pred;
     int32_t vec_stride, f32_stride, W, d, R, entry;
     int32_t adj_words, scal_word_off, lab_word_off;  // adjacency row layout (words)
-    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder;
+    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder, warm;
     float delta, rho;
     int32_t ladder[JAG_LADDER_MAX];
 };
@@ -521,9 +521,9 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
     }
     __syncthreads();
     int cnt = 1, hint = 0, hops = 0, ndist = 1, nattr = 1;
-    // learned and trace modes keep every discovered vertex during the first
-    // four expansions (Lcap >= 1 + 4R), so the features do not depend on a beam
-    int ls = a.mode == 0 ? a.L : a.Lcap;
+    // learned and trace modes: the first four expansions use the full list
+    // width (see plan_search), so the features do not depend on the final beam
+    int ls = a.mode == 0 ? a.L : a.warm;
     int hopcap = a.max_hops > 0 ? a.max_hops : INT_MAX;
     int lhat = a.mode == 1 ? 0 : a.L;
     bool predicted = a.mode == 0;
@@ -851,14 +851,11 @@ ExactFn exact_for_ch(int ch)
     return nullptr;
 }
 
-// Measured on the range workload (L = 48): 2^11 slots beat 2^10 (fewer
-// repeated evaluations) and 2^12 (lower occupancy).
-int hash_size_for(int L)
-{
-    int h = 2048;
-    while (h < 24 * L && h < 4096) h <<= 1;
-    return h;
-}
+// Measured on the range workload: 2^11 slots beat 2^10 (fewer repeated
+// evaluations) and 2^12 (lower occupancy: at L = 96, 2^12 cost 17 %).
+constexpr int kDefaultHash = 2048;
+// List width of the first four expansions in learned and trace modes.
+constexpr int kWarmWidth = 128;
 
 }  // namespace
 
@@ -1109,12 +1106,14 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
         for (int i = 0; i < ix.pred.nladder; i++)
             if (a.ladder[i] < k) a.ladder[i] = k;
     }
-    if (S.learned != 0 && Lcap < 1 + 4 * ix.R) Lcap = 1 + 4 * ix.R;
+    // learned and trace modes run the first four expansions with a list of
+    // max(kWarmWidth, widest beam) entries: both modes see the same list when
+    // the features are taken, and cutting it to any beam <= that width then
+    // gives exactly the fixed-beam search's state
+    if (S.learned != 0 && Lcap < kWarmWidth) Lcap = kWarmWidth;
+    a.warm = Lcap;
     Lcap = (Lcap + 63) / 64 * 64;
-    // the table of discovered ids is sized by the working beam: in learned
-    // mode the beam after the fourth expansion, typically far below Lcap
-    int Lwork = S.learned == 1 ? ix.pred.ladder[ix.pred.nladder / 2] : S.L;
-    int H = S.hash_log2 ? (1 << S.hash_log2) : hash_size_for(Lwork);
+    int H = S.hash_log2 ? (1 << S.hash_log2) : kDefaultHash;
     a.Lcap = Lcap;
     a.Hmask = H - 1;
     fn = pick_search(ix.store, ix.vec_stride);

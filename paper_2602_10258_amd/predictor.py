@@ -17,8 +17,9 @@ import numpy as np
 
 from . import jag
 
-LADDER = np.array([10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 384],
-                  dtype=np.int32)
+# beams the predictor chooses from; the widest equals the library's warm-up
+# list width (128), so learned search needs no more LDS than fixed L = 128
+LADDER = np.array([10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128], dtype=np.int32)
 
 
 @dataclass

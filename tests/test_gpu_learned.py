@@ -86,7 +86,8 @@ def test_learned_search_matches_oracle(c1_small):
     self_ = _sel_feature(nv, w.n)
     for delta in (-2.0, 0.0, 1.5):
         g = gpu_search(idx, w.Q, w.F, w.pool, 10, 16, learned=1, delta=delta)
-        orc = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, 512, 10, learned=Pq, delta=delta,
+        # the first four expansions keep max(128, widest beam) = 128 entries on both sides
+        orc = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, 128, 10, learned=Pq, delta=delta,
                        rho=rho, ladder=ladder, sel_feature=self_)
         z = orc.y + delta
         safe = np.abs(z - np.round(z)) > 1e-4
