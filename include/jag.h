@@ -140,6 +140,9 @@ typedef struct {
                             discovered ids has 2^hash_log2 slots.  It only trades LDS
                             (occupancy) against repeated evaluations; results do not
                             depend on it. */
+    int32_t no_speculation; /* 0 = each step also fetches the runner-up unexpanded vertex
+                               and keeps its expansion only if Algorithm 1 would expand it
+                               next; 1 = one vertex per step.  Results are identical. */
 } jag_search_params;
 
 typedef struct {

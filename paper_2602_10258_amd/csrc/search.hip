@@ -24,6 +24,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "jag_internal.h"
@@ -51,7 +52,7 @@ struct SearchArgs {
     const uint16_t *pred;
     int32_t vec_stride, f32_stride, W, d, R, entry;
     int32_t adj_words, scal_word_off, lab_word_off;  // adjacency row layout (words)
-    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder, warm;
+    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder, warm, spec;
     float delta, rho;
     int32_t ladder[JAG_LADDER_MAX];
 };
@@ -129,29 +130,26 @@ __device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &
                      a.W >> 1);
 }
 
-__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr &at, const SearchArgs &a)
+__device__ __forceinline__ uint32_t range_dist(const FilterRecord &f, int64_t v)
 {
-    if (f.type == F_RANGE) {
-        int64_t v = at.scalar;
-        if (v < f.a) return (uint32_t)((int64_t)f.a - v);
-        if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
-        return 0u;
-    }
-    const uint32_t *w = at.w;
-    int nw = a.W >> 1;
-    // static loop bounds keep the (uniform) record in scalar registers
-    uint32_t present = 0;
+    if (v < f.a) return (uint32_t)((int64_t)f.a - v);
+    if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
+    return 0u;
+}
+
+__device__ __forceinline__ bool has_label(const ItemAttr &at, uint32_t l, int nw)
+{
+    bool hit = false;
 #pragma unroll
-    for (int i = 0; i < kMaxFilterLits; i++) {
-        if (i < f.nlit) {
-            uint32_t l = f.lits[i];
-            bool hit = false;
-#pragma unroll
-            for (int j = 0; j < 8; j++)
-                if (j < nw) hit |= ((w[j] & 0xFFFFu) == l) | ((w[j] >> 16) == l);
-            present |= (uint32_t)hit << i;
-        }
-    }
+    for (int j = 0; j < 8; j++)
+        if (j < nw) hit |= ((at.w[j] & 0xFFFFu) == l) | ((at.w[j] >> 16) == l);
+    return hit;
+}
+
+// dist_F of a label-type filter from the bitmask of its literals' labels
+// that the item carries
+__device__ __forceinline__ uint32_t label_dist(const FilterRecord &f, uint32_t present)
+{
     if (f.type == F_LABEL) return (present & 1u) ? 0u : 1u;
     if (f.type == F_SUBSET) return (uint32_t)(f.nlit - __builtin_popcount(present));
     uint32_t truth = present ^ f.negmask;
@@ -164,6 +162,42 @@ __device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr
         }
     }
     return best;
+}
+
+__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr &at, const SearchArgs &a)
+{
+    if (f.type == F_RANGE) return range_dist(f, at.scalar);
+    const int nw = a.W >> 1;
+    // static loop bounds keep the (uniform) record in scalar registers
+    uint32_t present = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxFilterLits; i++)
+        if (i < f.nlit) present |= (uint32_t)has_label(at, f.lits[i], nw) << i;
+    return label_dist(f, present);
+}
+
+// dist_F of two items at once (one pass over the filter's literals); a
+// single evaluation site keeps both attribute rows in registers
+__device__ __forceinline__ void dist_f_pair(const FilterRecord &f, const ItemAttr &at, const ItemAttr &at2,
+                                            const SearchArgs &a, uint32_t &df, uint32_t &df2)
+{
+    if (f.type == F_RANGE) {
+        df = range_dist(f, at.scalar);
+        df2 = range_dist(f, at2.scalar);
+        return;
+    }
+    const int nw = a.W >> 1;
+    uint32_t p1 = 0, p2 = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxFilterLits; i++) {
+        if (i < f.nlit) {
+            uint32_t l = f.lits[i];
+            p1 |= (uint32_t)has_label(at, l, nw) << i;
+            p2 |= (uint32_t)has_label(at2, l, nw) << i;
+        }
+    }
+    df = label_dist(f, p1);
+    df2 = label_dist(f, p2);
 }
 
 // ---------------------------------------------------------------- distances
@@ -186,10 +220,10 @@ struct StoreTraits<JAG_STORE_FP8_E4M3> {
 // of the 16-byte chunks j*G + sub of a row (zero beyond d).
 template <int STORE, int G, int CH>
 struct QueryRegs {
-    float v[CH][StoreTraits<STORE>::EPC];
+    static constexpr int EPC = StoreTraits<STORE>::EPC;
+    float v[CH][EPC];
     __device__ __forceinline__ void load(const float *q, int d, int sub)
     {
-        constexpr int EPC = StoreTraits<STORE>::EPC;
 #pragma unroll
         for (int j = 0; j < CH; j++)
 #pragma unroll
@@ -198,7 +232,21 @@ struct QueryRegs {
                 v[j][e] = idx < d ? q[idx] : 0.f;
             }
     }
+    __device__ __forceinline__ float at(int j, int e) const { return v[j][e]; }
 };
+
+// The same view of the query kept in LDS (one copy per wavefront, zero
+// padded to the row length): frees CH x EPC registers per lane.
+template <int STORE, int G, int CH>
+struct QueryLds {
+    static constexpr int EPC = StoreTraits<STORE>::EPC;
+    const float *qs;
+    int sub;
+    __device__ __forceinline__ float at(int j, int e) const { return qs[(j * G + sub) * EPC + e]; }
+};
+
+// Where the search kernel keeps the query.
+constexpr bool kQueryInLds = true;
 
 __device__ __forceinline__ float acc_sq(float acc, float qv, float x)
 {
@@ -208,9 +256,8 @@ __device__ __forceinline__ float acc_sq(float acc, float qv, float x)
 
 // Partial squared distance of one row held by a G-lane group; the partial
 // sums of the group are then added in a fixed butterfly order.
-template <int STORE, int G, int CH>
-__device__ __forceinline__ float row_dist(const unsigned char *row, const QueryRegs<STORE, G, CH> &q,
-                                          int sub)
+template <int STORE, int G, int CH, class QV>
+__device__ __forceinline__ float row_dist(const unsigned char *row, const QV &q, int sub)
 {
     uint4 c[CH];
 #pragma unroll
@@ -220,10 +267,10 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QueryR
     if constexpr (STORE == JAG_STORE_F32) {
 #pragma unroll
         for (int j = 0; j < CH; j++) {
-            acc = acc_sq(acc, q.v[j][0], __uint_as_float(c[j].x));
-            acc = acc_sq(acc, q.v[j][1], __uint_as_float(c[j].y));
-            acc = acc_sq(acc, q.v[j][2], __uint_as_float(c[j].z));
-            acc = acc_sq(acc, q.v[j][3], __uint_as_float(c[j].w));
+            acc = acc_sq(acc, q.at(j, 0), __uint_as_float(c[j].x));
+            acc = acc_sq(acc, q.at(j, 1), __uint_as_float(c[j].y));
+            acc = acc_sq(acc, q.at(j, 2), __uint_as_float(c[j].z));
+            acc = acc_sq(acc, q.at(j, 3), __uint_as_float(c[j].w));
         }
     } else if constexpr (STORE == JAG_STORE_BF16) {
 #pragma unroll
@@ -231,8 +278,8 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QueryR
             uint32_t w[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-                acc = acc_sq(acc, q.v[j][2 * t], __uint_as_float(w[t] << 16));
-                acc = acc_sq(acc, q.v[j][2 * t + 1], __uint_as_float(w[t] & 0xFFFF0000u));
+                acc = acc_sq(acc, q.at(j, 2 * t), __uint_as_float(w[t] << 16));
+                acc = acc_sq(acc, q.at(j, 2 * t + 1), __uint_as_float(w[t] & 0xFFFF0000u));
             }
         }
     } else {
@@ -247,10 +294,10 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QueryR
                 if (j == CH - 1 && t == 3 && sub == G - 1) continue;  // the scale, not codes
                 auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[t], false);
                 auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[t], true);
-                acc = acc_sq(acc, q.v[j][4 * t + 0], s * lo[0]);
-                acc = acc_sq(acc, q.v[j][4 * t + 1], s * lo[1]);
-                acc = acc_sq(acc, q.v[j][4 * t + 2], s * hi[0]);
-                acc = acc_sq(acc, q.v[j][4 * t + 3], s * hi[1]);
+                acc = acc_sq(acc, q.at(j, 4 * t + 0), s * lo[0]);
+                acc = acc_sq(acc, q.at(j, 4 * t + 1), s * lo[1]);
+                acc = acc_sq(acc, q.at(j, 4 * t + 2), s * hi[0]);
+                acc = acc_sq(acc, q.at(j, 4 * t + 3), s * hi[1]);
             }
         }
     }
@@ -260,22 +307,19 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QueryR
 }
 
 // Squared distances of the m candidates cid[0..m) into cd2[], G lanes per row.
-template <int STORE, int G, int CH>
+template <int STORE, int G, int CH, class QV>
 __device__ __forceinline__ void eval_rows(const unsigned char *base, int stride, const int32_t *cid,
-                                          float *cd2, int m, const QueryRegs<STORE, G, CH> &q)
+                                          float *cd2, int m, const QV &q)
 {
     const int lane = threadIdx.x;
     const int sub = lane & (G - 1), grp = lane / G;
     constexpr int P = 64 / G;
-    for (int r = 0; r < m; r += 2 * P) {
-        int c0 = r + grp, c1 = r + P + grp;
+    for (int r = 0; r < m; r += P) {
+        int c0 = r + grp;
         // rows past m re-read row cid[0] so every lane stays in bounds
-        int i0 = cid[c0 < m ? c0 : 0], i1 = cid[c1 < m ? c1 : 0];
+        int i0 = cid[c0 < m ? c0 : 0];
         float d0 = row_dist<STORE, G, CH>(base + (int64_t)i0 * stride, q, sub);
-        float d1 = 0.f;
-        if (r + P < m) d1 = row_dist<STORE, G, CH>(base + (int64_t)i1 * stride, q, sub);
         if (sub == 0 && c0 < m) cd2[c0] = d0;
-        if (sub == 0 && c1 < m) cd2[c1] = d1;
     }
 }
 
@@ -310,6 +354,7 @@ struct Lds {
     float *feat;
     float *h1;
     uint64_t *exkey;
+    float *qs;  // the query, when kept in LDS
 };
 
 __device__ __forceinline__ Lds carve(unsigned char *smem, int Lcap, int H)
@@ -320,20 +365,35 @@ __device__ __forceinline__ Lds carve(unsigned char *smem, int Lcap, int H)
     s.exkey = s.skey + 64;
     s.idf = reinterpret_cast<uint32_t *>(s.exkey + 4);
     s.hash = reinterpret_cast<int32_t *>(s.idf + Lcap);
-    s.cid = s.hash + H;
-    s.cdf = reinterpret_cast<uint32_t *>(s.cid + 64);
-    s.cd2 = reinterpret_cast<float *>(s.cdf + 64);
-    s.sid = reinterpret_cast<uint32_t *>(s.cd2 + 64);
+    s.cid = s.hash + H;  // candidate slots: 64 for the expanded vertex + 64 for the runner-up
+    s.cdf = reinterpret_cast<uint32_t *>(s.cid + 128);
+    s.cd2 = reinterpret_cast<float *>(s.cdf + 128);
+    s.sid = reinterpret_cast<uint32_t *>(s.cd2 + 128);
     s.spos = reinterpret_cast<int32_t *>(s.sid + 64);
     s.feat = reinterpret_cast<float *>(s.spos + 64);
     s.h1 = s.feat + 16;
+    s.qs = s.h1 + 64;
     return s;
 }
 
-__host__ __device__ constexpr size_t lds_bytes(int Lcap, int H)
+// qn: query elements kept in LDS (0 when the query lives in registers)
+__host__ __device__ constexpr size_t lds_bytes(int Lcap, int H, int qn)
 {
-    return (size_t)Lcap * 8 + 64 * 8 + 4 * 8 + (size_t)Lcap * 4 + (size_t)H * 4 + 64 * 4 * 6 + 16 * 4 +
-           64 * 4;
+    return (size_t)Lcap * 8 + 64 * 8 + 4 * 8 + (size_t)Lcap * 4 + (size_t)H * 4 + 128 * 4 * 3 +
+           64 * 4 * 2 + 16 * 4 + 64 * 4 + (size_t)qn * 4;
+}
+
+// Is id u in the hash?  (never true for an id that was not inserted)
+__device__ __forceinline__ bool hash_find(const int32_t *hash, int mask, int32_t u)
+{
+    uint32_t h = (uint32_t)u * 0x9E3779B1u;
+    h ^= h >> 15;
+    for (int t = 0; t < 4; t++) {
+        int32_t v = hash[(h + t) & (uint32_t)mask];
+        if (v == u) return true;
+        if (v == -1) return false;
+    }
+    return false;
 }
 
 // Insert id u into the lossy hash; true if u was not found (newly seen).
@@ -367,18 +427,19 @@ __device__ __forceinline__ int first_unexpanded(const Lds &s, int from, int cnt)
     return cnt;
 }
 
-// Merge candidates (lane c < m holds cid/cdf/cd2 slot c) into the sorted
-// list of cnt entries, keeping at most ls.  Returns the new size; *minpos is
-// the list position of the best inserted candidate (ls if none).
-__device__ int merge_candidates(const Lds &s, int m, int cnt, int ls, int *minpos)
+// Merge candidates (lane c < m holds cid/cdf/cd2 slot off + c) into the
+// sorted list of cnt entries, keeping at most ls.  Returns the new size;
+// *minpos is the list position of the best inserted candidate (ls if none).
+__device__ __forceinline__ int merge_candidates(const Lds &s, int off, int m, int cnt, int ls,
+                                                int *minpos)
 {
     const int lane = threadIdx.x;
     bool have = lane < m;
     uint64_t ck = 0;
     uint32_t ci = 0;
     if (have) {
-        ck = ((uint64_t)s.cdf[lane] << 32) | __float_as_uint(s.cd2[lane]);
-        ci = (uint32_t)s.cid[lane];
+        ck = ((uint64_t)s.cdf[off + lane] << 32) | __float_as_uint(s.cd2[off + lane]);
+        ci = (uint32_t)s.cid[off + lane];
     }
     if (have && cnt == ls) {
         uint64_t wk = s.key[cnt - 1];
@@ -470,7 +531,7 @@ __device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uin
 
 // Beam predictor: 16 -> 64 -> 64 -> 1, ReLU, BF16 weights, FP32 sums.
 // Lane j computes hidden unit j; the output is a butterfly sum over lanes.
-__device__ float predict(const Lds &s, const uint16_t *P)
+__device__ __forceinline__ float predict(const Lds &s, const uint16_t *P)
 {
     const int lane = threadIdx.x;
     const uint16_t *W1 = P, *b1 = P + 1024, *W2 = P + 1088, *b2 = P + 5184, *w3 = P + 5248,
@@ -491,7 +552,9 @@ __device__ float predict(const Lds &s, const uint16_t *P)
 }
 
 template <int STORE, int G, int CH>
-__global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
+// at least 4 waves per SIMD: 128 VGPRs; LDS holds a list of 64 plus the
+// 2^11-slot table to about 14 queries per CU anyway
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
@@ -500,8 +563,16 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
     Lds s = carve(smem, a.Lcap, H);
     const FilterRecord f = a.rec[q];
     const float *qv = a.Q + q * a.d;
-    QueryRegs<STORE, G, CH> qr;
-    qr.load(qv, a.d, lane & (G - 1));
+    using QV = std::conditional_t<kQueryInLds, QueryLds<STORE, G, CH>, QueryRegs<STORE, G, CH>>;
+    QV qr;
+    if constexpr (kQueryInLds) {
+        constexpr int QN = CH * G * StoreTraits<STORE>::EPC;  // elements per stored row
+        for (int i = lane; i < QN; i += 64) s.qs[i] = i < a.d ? qv[i] : 0.f;
+        qr.qs = s.qs;
+        qr.sub = lane & (G - 1);
+    } else {
+        qr.load(qv, a.d, lane & (G - 1));
+    }
     for (int i = lane; i < H; i += 64) s.hash[i] = -1;
 
     // L <- {s}
@@ -531,41 +602,89 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
         hint = first_unexpanded(s, hint, cnt);
         if (hint >= cnt || hops >= hopcap) break;
         const int p = (int)(s.idf[hint] & kIdMask);
+        // Runner-up: the next unexpanded vertex.  Its row, attributes and
+        // vectors are fetched together with p's; after p's candidates are
+        // merged it is expanded only if it is then the first unexpanded
+        // vertex, i.e. exactly the vertex Algorithm 1 expands next.  (The
+        // fourth expansion is never speculative: the predictor reads the
+        // list right after it.)
+        bool spec = a.spec && hops + 2 <= hopcap && (predicted || hops != 3);
+        const int h2 = spec ? first_unexpanded(s, hint + 1, cnt) : cnt;
+        spec = h2 < cnt;
+        const int p2 = spec ? (int)(s.idf[h2] & kIdMask) : 0;
         __syncthreads();
         if (lane == 0) {
             s.idf[hint] |= kExpanded;
             if (hops < 4) s.exkey[hops] = s.key[hint];
         }
         hops++;
-        // one row holds the neighbour ids and their attribute words: both
+        // one row holds the neighbour ids and their attribute words: all
         // loads are issued together, before the ids are known
         const int32_t *row = a.adj + (int64_t)p * a.adj_words;
-        int32_t u = -1;
-        ItemAttr at;
+        const int32_t *row2 = a.adj + (int64_t)p2 * a.adj_words;
+        int32_t u = -1, u2 = -1;
+        ItemAttr at, at2;
         if (lane < a.R) {
             u = row[lane];
             load_row_attr(at, f, row, lane, a);
+            if (spec) {
+                u2 = row2[lane];
+                load_row_attr(at2, f, row2, lane, a);
+            }
         }
         bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
-        uint32_t df = fresh ? dist_f(f, at, a) : 0u;
-        nattr += __popcll(ballot64(fresh));
-        if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
-        uint64_t bm = ballot64(fresh);
-        int m = __popcll(bm);
+        __syncthreads();
+        // the runner-up's neighbours are looked up after p's are inserted, as
+        // they would be if it were expanded next; they are inserted on commit
+        const bool unseen2 = spec && u2 >= 0 && !hash_find(s.hash, a.Hmask, u2);
+        bool fresh2 = unseen2;
+        uint32_t df, df2;
+        dist_f_pair(f, at, at2, a, df, df2);
+        df = fresh ? df : 0u;
+        df2 = fresh2 ? df2 : 0u;
+        nattr += __popcll(ballot64(fresh)) + __popcll(ballot64(fresh2));
+        if (cnt == ls) {
+            const uint32_t wdf = (uint32_t)(s.key[cnt - 1] >> 32);
+            fresh = fresh && df <= wdf;
+            fresh2 = fresh2 && df2 <= wdf;
+        }
+        const uint64_t bm = ballot64(fresh), bm2 = ballot64(fresh2);
+        const int m = __popcll(bm), m2 = __popcll(bm2);
         if (fresh) {
             int slot = lanes_below(bm);
             s.cid[slot] = u;
             s.cdf[slot] = df;
         }
-        __syncthreads();
-        int minpos = INT_MAX;
-        if (m > 0) {
-            eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
-            __syncthreads();
-            ndist += m;
-            cnt = merge_candidates(s, m, cnt, ls, &minpos);
+        if (fresh2) {
+            int slot = m + lanes_below(bm2);
+            s.cid[slot] = u2;
+            s.cdf[slot] = df2;
         }
+        __syncthreads();
+        if (m + m2 > 0) {
+            eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m + m2, qr);
+            __syncthreads();
+            ndist += m + m2;
+        }
+        int minpos = INT_MAX;
+        if (m > 0) cnt = merge_candidates(s, 0, m, cnt, ls, &minpos);
         hint = minpos < hint + 1 ? minpos : hint + 1;
+        if (spec) {
+            const int hn = first_unexpanded(s, hint, cnt);
+            if (hn < cnt && (int)(s.idf[hn] & kIdMask) == p2) {
+                __syncthreads();
+                if (lane == 0) {
+                    s.idf[hn] |= kExpanded;
+                    if (hops < 4) s.exkey[hops] = s.key[hn];
+                }
+                hops++;
+                if (unseen2) hash_insert(s.hash, a.Hmask, u2);
+                __syncthreads();
+                int mp2 = INT_MAX;
+                if (m2 > 0) cnt = merge_candidates(s, m, m2, cnt, ls, &mp2);
+                hint = mp2 < hn + 1 ? mp2 : hn + 1;
+            }
+        }
         if (!predicted && hops == 4) {
             predicted = true;
             // predictor features after the fourth expansion
@@ -706,7 +825,7 @@ __global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
         eval_rows<JAG_STORE_F32, G, CH>(a.f32, a.f32_stride, s.cid, s.cd2, m, qr);
         __syncthreads();
         int mp;
-        cnt = merge_candidates(s, m, cnt, a.k, &mp);
+        cnt = merge_candidates(s, 0, m, cnt, a.k, &mp);
     }
     bool ok = lane < cnt && lane < a.k;
     if (lane < a.k) {
@@ -1093,6 +1212,7 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
     a.delta = S.delta;
     a.rerank = S.rerank_mult;
     a.max_hops = S.max_hops;
+    a.spec = S.no_speculation ? 0 : 1;
     a.nladder = ix.pred.nladder;
     a.rho = ix.pred.rho;
     for (int i = 0; i < JAG_LADDER_MAX; i++) a.ladder[i] = ix.pred.ladder[i];
@@ -1121,7 +1241,8 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
         set_error("no kernel for row stride %d", ix.vec_stride);
         return JAG_EUNSUPPORTED;
     }
-    lds = lds_bytes(Lcap, H);
+    const int eb = ix.store == JAG_STORE_F32 ? 4 : ix.store == JAG_STORE_BF16 ? 2 : 1;
+    lds = lds_bytes(Lcap, H, kQueryInLds ? ix.vec_stride / eb : 0);
     return JAG_OK;
 }
 
@@ -1181,7 +1302,7 @@ jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *recor
         set_error("no exact kernel for FP32 row stride %d", ix.f32_stride);
         return JAG_EUNSUPPORTED;
     }
-    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds_bytes(64, 1), (hipStream_t)stream, a, ix.n);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds_bytes(64, 1, 0), (hipStream_t)stream, a, ix.n);
     HIPCHK(hipGetLastError());
     return JAG_OK;
 }
