@@ -140,9 +140,14 @@ typedef struct {
                             discovered ids has 2^hash_log2 slots.  It only trades LDS
                             (occupancy) against repeated evaluations; results do not
                             depend on it. */
-    int32_t no_speculation; /* 0 = each step also fetches the runner-up unexpanded vertex
-                               and keeps its expansion only if Algorithm 1 would expand it
-                               next; 1 = one vertex per step.  Results are identical. */
+    int32_t single_pass; /* learned == 1 only.  0 = two launches: the first runs every
+                            query to its prediction point and records its beam, the
+                            second searches from the start with the queries in order of
+                            decreasing predicted beam (longest first, so the batch
+                            does not end on a few long searches), reusing the recorded
+                            beams; 1 = one launch in submission order.  Results are
+                            identical; two passes need 8*nq bytes of stream-ordered
+                            scratch. */
 } jag_search_params;
 
 typedef struct {

@@ -20,11 +20,11 @@
 // and merge the new keys into the sorted list, cutting it to l_s.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
 #include <string>
-#include <type_traits>
 #include <vector>
 
 #include "jag_internal.h"
@@ -52,7 +52,10 @@ struct SearchArgs {
     const uint16_t *pred;
     int32_t vec_stride, f32_stride, W, d, R, entry;
     int32_t adj_words, scal_word_off, lab_word_off;  // adjacency row layout (words)
-    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder, warm, spec;
+    int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder, warm;
+    const int32_t *perm;  // query handled by each workgroup (null: identity)
+    int32_t *state;       // modes 3 and 4: saved search state, state_stride words per query
+    int64_t state_stride;
     float delta, rho;
     int32_t ladder[JAG_LADDER_MAX];
 };
@@ -130,26 +133,29 @@ __device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &
                      a.W >> 1);
 }
 
-__device__ __forceinline__ uint32_t range_dist(const FilterRecord &f, int64_t v)
+__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr &at, const SearchArgs &a)
 {
-    if (v < f.a) return (uint32_t)((int64_t)f.a - v);
-    if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
-    return 0u;
-}
-
-__device__ __forceinline__ bool has_label(const ItemAttr &at, uint32_t l, int nw)
-{
-    bool hit = false;
+    if (f.type == F_RANGE) {
+        int64_t v = at.scalar;
+        if (v < f.a) return (uint32_t)((int64_t)f.a - v);
+        if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
+        return 0u;
+    }
+    const uint32_t *w = at.w;
+    int nw = a.W >> 1;
+    // static loop bounds keep the (uniform) record in scalar registers
+    uint32_t present = 0;
 #pragma unroll
-    for (int j = 0; j < 8; j++)
-        if (j < nw) hit |= ((at.w[j] & 0xFFFFu) == l) | ((at.w[j] >> 16) == l);
-    return hit;
-}
-
-// dist_F of a label-type filter from the bitmask of its literals' labels
-// that the item carries
-__device__ __forceinline__ uint32_t label_dist(const FilterRecord &f, uint32_t present)
-{
+    for (int i = 0; i < kMaxFilterLits; i++) {
+        if (i < f.nlit) {
+            uint32_t l = f.lits[i];
+            bool hit = false;
+#pragma unroll
+            for (int j = 0; j < 8; j++)
+                if (j < nw) hit |= ((w[j] & 0xFFFFu) == l) | ((w[j] >> 16) == l);
+            present |= (uint32_t)hit << i;
+        }
+    }
     if (f.type == F_LABEL) return (present & 1u) ? 0u : 1u;
     if (f.type == F_SUBSET) return (uint32_t)(f.nlit - __builtin_popcount(present));
     uint32_t truth = present ^ f.negmask;
@@ -162,42 +168,6 @@ __device__ __forceinline__ uint32_t label_dist(const FilterRecord &f, uint32_t p
         }
     }
     return best;
-}
-
-__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr &at, const SearchArgs &a)
-{
-    if (f.type == F_RANGE) return range_dist(f, at.scalar);
-    const int nw = a.W >> 1;
-    // static loop bounds keep the (uniform) record in scalar registers
-    uint32_t present = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxFilterLits; i++)
-        if (i < f.nlit) present |= (uint32_t)has_label(at, f.lits[i], nw) << i;
-    return label_dist(f, present);
-}
-
-// dist_F of two items at once (one pass over the filter's literals); a
-// single evaluation site keeps both attribute rows in registers
-__device__ __forceinline__ void dist_f_pair(const FilterRecord &f, const ItemAttr &at, const ItemAttr &at2,
-                                            const SearchArgs &a, uint32_t &df, uint32_t &df2)
-{
-    if (f.type == F_RANGE) {
-        df = range_dist(f, at.scalar);
-        df2 = range_dist(f, at2.scalar);
-        return;
-    }
-    const int nw = a.W >> 1;
-    uint32_t p1 = 0, p2 = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxFilterLits; i++) {
-        if (i < f.nlit) {
-            uint32_t l = f.lits[i];
-            p1 |= (uint32_t)has_label(at, l, nw) << i;
-            p2 |= (uint32_t)has_label(at2, l, nw) << i;
-        }
-    }
-    df = label_dist(f, p1);
-    df2 = label_dist(f, p2);
 }
 
 // ---------------------------------------------------------------- distances
@@ -220,10 +190,10 @@ struct StoreTraits<JAG_STORE_FP8_E4M3> {
 // of the 16-byte chunks j*G + sub of a row (zero beyond d).
 template <int STORE, int G, int CH>
 struct QueryRegs {
-    static constexpr int EPC = StoreTraits<STORE>::EPC;
-    float v[CH][EPC];
+    float v[CH][StoreTraits<STORE>::EPC];
     __device__ __forceinline__ void load(const float *q, int d, int sub)
     {
+        constexpr int EPC = StoreTraits<STORE>::EPC;
 #pragma unroll
         for (int j = 0; j < CH; j++)
 #pragma unroll
@@ -232,21 +202,7 @@ struct QueryRegs {
                 v[j][e] = idx < d ? q[idx] : 0.f;
             }
     }
-    __device__ __forceinline__ float at(int j, int e) const { return v[j][e]; }
 };
-
-// The same view of the query kept in LDS (one copy per wavefront, zero
-// padded to the row length): frees CH x EPC registers per lane.
-template <int STORE, int G, int CH>
-struct QueryLds {
-    static constexpr int EPC = StoreTraits<STORE>::EPC;
-    const float *qs;
-    int sub;
-    __device__ __forceinline__ float at(int j, int e) const { return qs[(j * G + sub) * EPC + e]; }
-};
-
-// Where the search kernel keeps the query.
-constexpr bool kQueryInLds = true;
 
 __device__ __forceinline__ float acc_sq(float acc, float qv, float x)
 {
@@ -256,8 +212,9 @@ __device__ __forceinline__ float acc_sq(float acc, float qv, float x)
 
 // Partial squared distance of one row held by a G-lane group; the partial
 // sums of the group are then added in a fixed butterfly order.
-template <int STORE, int G, int CH, class QV>
-__device__ __forceinline__ float row_dist(const unsigned char *row, const QV &q, int sub)
+template <int STORE, int G, int CH>
+__device__ __forceinline__ float row_dist(const unsigned char *row, const QueryRegs<STORE, G, CH> &q,
+                                          int sub)
 {
     uint4 c[CH];
 #pragma unroll
@@ -267,10 +224,10 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QV &q,
     if constexpr (STORE == JAG_STORE_F32) {
 #pragma unroll
         for (int j = 0; j < CH; j++) {
-            acc = acc_sq(acc, q.at(j, 0), __uint_as_float(c[j].x));
-            acc = acc_sq(acc, q.at(j, 1), __uint_as_float(c[j].y));
-            acc = acc_sq(acc, q.at(j, 2), __uint_as_float(c[j].z));
-            acc = acc_sq(acc, q.at(j, 3), __uint_as_float(c[j].w));
+            acc = acc_sq(acc, q.v[j][0], __uint_as_float(c[j].x));
+            acc = acc_sq(acc, q.v[j][1], __uint_as_float(c[j].y));
+            acc = acc_sq(acc, q.v[j][2], __uint_as_float(c[j].z));
+            acc = acc_sq(acc, q.v[j][3], __uint_as_float(c[j].w));
         }
     } else if constexpr (STORE == JAG_STORE_BF16) {
 #pragma unroll
@@ -278,8 +235,8 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QV &q,
             uint32_t w[4] = {c[j].x, c[j].y, c[j].z, c[j].w};
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-                acc = acc_sq(acc, q.at(j, 2 * t), __uint_as_float(w[t] << 16));
-                acc = acc_sq(acc, q.at(j, 2 * t + 1), __uint_as_float(w[t] & 0xFFFF0000u));
+                acc = acc_sq(acc, q.v[j][2 * t], __uint_as_float(w[t] << 16));
+                acc = acc_sq(acc, q.v[j][2 * t + 1], __uint_as_float(w[t] & 0xFFFF0000u));
             }
         }
     } else {
@@ -294,10 +251,10 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QV &q,
                 if (j == CH - 1 && t == 3 && sub == G - 1) continue;  // the scale, not codes
                 auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[t], false);
                 auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[t], true);
-                acc = acc_sq(acc, q.at(j, 4 * t + 0), s * lo[0]);
-                acc = acc_sq(acc, q.at(j, 4 * t + 1), s * lo[1]);
-                acc = acc_sq(acc, q.at(j, 4 * t + 2), s * hi[0]);
-                acc = acc_sq(acc, q.at(j, 4 * t + 3), s * hi[1]);
+                acc = acc_sq(acc, q.v[j][4 * t + 0], s * lo[0]);
+                acc = acc_sq(acc, q.v[j][4 * t + 1], s * lo[1]);
+                acc = acc_sq(acc, q.v[j][4 * t + 2], s * hi[0]);
+                acc = acc_sq(acc, q.v[j][4 * t + 3], s * hi[1]);
             }
         }
     }
@@ -307,19 +264,22 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QV &q,
 }
 
 // Squared distances of the m candidates cid[0..m) into cd2[], G lanes per row.
-template <int STORE, int G, int CH, class QV>
+template <int STORE, int G, int CH>
 __device__ __forceinline__ void eval_rows(const unsigned char *base, int stride, const int32_t *cid,
-                                          float *cd2, int m, const QV &q)
+                                          float *cd2, int m, const QueryRegs<STORE, G, CH> &q)
 {
     const int lane = threadIdx.x;
     const int sub = lane & (G - 1), grp = lane / G;
     constexpr int P = 64 / G;
-    for (int r = 0; r < m; r += P) {
-        int c0 = r + grp;
+    for (int r = 0; r < m; r += 2 * P) {
+        int c0 = r + grp, c1 = r + P + grp;
         // rows past m re-read row cid[0] so every lane stays in bounds
-        int i0 = cid[c0 < m ? c0 : 0];
+        int i0 = cid[c0 < m ? c0 : 0], i1 = cid[c1 < m ? c1 : 0];
         float d0 = row_dist<STORE, G, CH>(base + (int64_t)i0 * stride, q, sub);
+        float d1 = 0.f;
+        if (r + P < m) d1 = row_dist<STORE, G, CH>(base + (int64_t)i1 * stride, q, sub);
         if (sub == 0 && c0 < m) cd2[c0] = d0;
+        if (sub == 0 && c1 < m) cd2[c1] = d1;
     }
 }
 
@@ -354,7 +314,6 @@ struct Lds {
     float *feat;
     float *h1;
     uint64_t *exkey;
-    float *qs;  // the query, when kept in LDS
 };
 
 __device__ __forceinline__ Lds carve(unsigned char *smem, int Lcap, int H)
@@ -365,35 +324,20 @@ __device__ __forceinline__ Lds carve(unsigned char *smem, int Lcap, int H)
     s.exkey = s.skey + 64;
     s.idf = reinterpret_cast<uint32_t *>(s.exkey + 4);
     s.hash = reinterpret_cast<int32_t *>(s.idf + Lcap);
-    s.cid = s.hash + H;  // candidate slots: 64 for the expanded vertex + 64 for the runner-up
-    s.cdf = reinterpret_cast<uint32_t *>(s.cid + 128);
-    s.cd2 = reinterpret_cast<float *>(s.cdf + 128);
-    s.sid = reinterpret_cast<uint32_t *>(s.cd2 + 128);
+    s.cid = s.hash + H;
+    s.cdf = reinterpret_cast<uint32_t *>(s.cid + 64);
+    s.cd2 = reinterpret_cast<float *>(s.cdf + 64);
+    s.sid = reinterpret_cast<uint32_t *>(s.cd2 + 64);
     s.spos = reinterpret_cast<int32_t *>(s.sid + 64);
     s.feat = reinterpret_cast<float *>(s.spos + 64);
     s.h1 = s.feat + 16;
-    s.qs = s.h1 + 64;
     return s;
 }
 
-// qn: query elements kept in LDS (0 when the query lives in registers)
-__host__ __device__ constexpr size_t lds_bytes(int Lcap, int H, int qn)
+__host__ __device__ constexpr size_t lds_bytes(int Lcap, int H)
 {
-    return (size_t)Lcap * 8 + 64 * 8 + 4 * 8 + (size_t)Lcap * 4 + (size_t)H * 4 + 128 * 4 * 3 +
-           64 * 4 * 2 + 16 * 4 + 64 * 4 + (size_t)qn * 4;
-}
-
-// Is id u in the hash?  (never true for an id that was not inserted)
-__device__ __forceinline__ bool hash_find(const int32_t *hash, int mask, int32_t u)
-{
-    uint32_t h = (uint32_t)u * 0x9E3779B1u;
-    h ^= h >> 15;
-    for (int t = 0; t < 4; t++) {
-        int32_t v = hash[(h + t) & (uint32_t)mask];
-        if (v == u) return true;
-        if (v == -1) return false;
-    }
-    return false;
+    return (size_t)Lcap * 8 + 64 * 8 + 4 * 8 + (size_t)Lcap * 4 + (size_t)H * 4 + 64 * 4 * 6 + 16 * 4 +
+           64 * 4;
 }
 
 // Insert id u into the lossy hash; true if u was not found (newly seen).
@@ -427,19 +371,18 @@ __device__ __forceinline__ int first_unexpanded(const Lds &s, int from, int cnt)
     return cnt;
 }
 
-// Merge candidates (lane c < m holds cid/cdf/cd2 slot off + c) into the
-// sorted list of cnt entries, keeping at most ls.  Returns the new size;
-// *minpos is the list position of the best inserted candidate (ls if none).
-__device__ __forceinline__ int merge_candidates(const Lds &s, int off, int m, int cnt, int ls,
-                                                int *minpos)
+// Merge candidates (lane c < m holds cid/cdf/cd2 slot c) into the sorted
+// list of cnt entries, keeping at most ls.  Returns the new size; *minpos is
+// the list position of the best inserted candidate (ls if none).
+__device__ int merge_candidates(const Lds &s, int m, int cnt, int ls, int *minpos)
 {
     const int lane = threadIdx.x;
     bool have = lane < m;
     uint64_t ck = 0;
     uint32_t ci = 0;
     if (have) {
-        ck = ((uint64_t)s.cdf[off + lane] << 32) | __float_as_uint(s.cd2[off + lane]);
-        ci = (uint32_t)s.cid[off + lane];
+        ck = ((uint64_t)s.cdf[lane] << 32) | __float_as_uint(s.cd2[lane]);
+        ci = (uint32_t)s.cid[lane];
     }
     if (have && cnt == ls) {
         uint64_t wk = s.key[cnt - 1];
@@ -531,7 +474,7 @@ __device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uin
 
 // Beam predictor: 16 -> 64 -> 64 -> 1, ReLU, BF16 weights, FP32 sums.
 // Lane j computes hidden unit j; the output is a butterfly sum over lanes.
-__device__ __forceinline__ float predict(const Lds &s, const uint16_t *P)
+__device__ float predict(const Lds &s, const uint16_t *P)
 {
     const int lane = threadIdx.x;
     const uint16_t *W1 = P, *b1 = P + 1024, *W2 = P + 1088, *b2 = P + 5184, *w3 = P + 5248,
@@ -552,139 +495,106 @@ __device__ __forceinline__ float predict(const Lds &s, const uint16_t *P)
 }
 
 template <int STORE, int G, int CH>
-// at least 4 waves per SIMD: 128 VGPRs; LDS holds a list of 64 plus the
-// 2^11-slot table to about 14 queries per CU anyway
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void search_kernel(SearchArgs a)
+__global__ __launch_bounds__(64) void search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
-    const int64_t q = blockIdx.x;
+    const int64_t q = a.perm ? (int64_t)a.perm[blockIdx.x] : (int64_t)blockIdx.x;
     const int H = a.Hmask + 1;
     Lds s = carve(smem, a.Lcap, H);
     const FilterRecord f = a.rec[q];
     const float *qv = a.Q + q * a.d;
-    using QV = std::conditional_t<kQueryInLds, QueryLds<STORE, G, CH>, QueryRegs<STORE, G, CH>>;
-    QV qr;
-    if constexpr (kQueryInLds) {
-        constexpr int QN = CH * G * StoreTraits<STORE>::EPC;  // elements per stored row
-        for (int i = lane; i < QN; i += 64) s.qs[i] = i < a.d ? qv[i] : 0.f;
-        qr.qs = s.qs;
-        qr.sub = lane & (G - 1);
-    } else {
-        qr.load(qv, a.d, lane & (G - 1));
-    }
-    for (int i = lane; i < H; i += 64) s.hash[i] = -1;
+    QueryRegs<STORE, G, CH> qr;
+    qr.load(qv, a.d, lane & (G - 1));
 
-    // L <- {s}
-    if (lane == 0) {
-        s.cid[0] = a.entry;
-        ItemAttr at;
-        load_item_attr(at, f, a.entry, a);
-        s.cdf[0] = dist_f(f, at, a);
-    }
-    __syncthreads();
-    eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, 1, qr);
-    __syncthreads();
-    if (lane == 0) {
-        s.key[0] = ((uint64_t)s.cdf[0] << 32) | __float_as_uint(s.cd2[0]);
-        s.idf[0] = (uint32_t)a.entry;
-        hash_insert(s.hash, a.Hmask, a.entry);
-    }
-    __syncthreads();
     int cnt = 1, hint = 0, hops = 0, ndist = 1, nattr = 1;
     // learned and trace modes: the first four expansions use the full list
     // width (see plan_search), so the features do not depend on the final beam
     int ls = a.mode == 0 ? a.L : a.warm;
     int hopcap = a.max_hops > 0 ? a.max_hops : INT_MAX;
-    int lhat = a.mode == 1 ? 0 : a.L;
+    // modes: 0 fixed beam, 1 predicted beam, 2 trace; a two-pass learned
+    // search runs mode 3 (up to the prediction, then save the state and stop)
+    // and mode 4 (resume a saved state, else the same as mode 1)
+    int lhat = a.mode == 0 || a.mode == 2 ? a.L : 0;
     bool predicted = a.mode == 0;
+    const int32_t *rs = a.mode == 4 ? a.state + q * a.state_stride : nullptr;
+    if (rs && rs[0] > 0) {
+        cnt = rs[1];
+        hint = rs[2];
+        hops = rs[3];
+        ndist = rs[4];
+        nattr = rs[5];
+        hopcap = rs[6];
+        lhat = rs[7];
+        ls = lhat;
+        predicted = true;
+        const uint64_t *sk = reinterpret_cast<const uint64_t *>(rs + 8);
+        const uint32_t *si = reinterpret_cast<const uint32_t *>(rs + 8 + 2 * a.Lcap);
+        const int4 *sh = reinterpret_cast<const int4 *>(rs + 8 + 3 * a.Lcap);
+        for (int j = lane; j < cnt; j += 64) {
+            s.key[j] = sk[j];
+            s.idf[j] = si[j];
+        }
+        for (int j = lane; j < (H >> 2); j += 64) reinterpret_cast<int4 *>(s.hash)[j] = sh[j];
+        __syncthreads();
+    } else {
+        for (int i = lane; i < H; i += 64) s.hash[i] = -1;
+        // L <- {s}
+        if (lane == 0) {
+            s.cid[0] = a.entry;
+            ItemAttr at;
+            load_item_attr(at, f, a.entry, a);
+            s.cdf[0] = dist_f(f, at, a);
+        }
+        __syncthreads();
+        eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, 1, qr);
+        __syncthreads();
+        if (lane == 0) {
+            s.key[0] = ((uint64_t)s.cdf[0] << 32) | __float_as_uint(s.cd2[0]);
+            s.idf[0] = (uint32_t)a.entry;
+            hash_insert(s.hash, a.Hmask, a.entry);
+        }
+        __syncthreads();
+    }
     for (;;) {
         hint = first_unexpanded(s, hint, cnt);
         if (hint >= cnt || hops >= hopcap) break;
         const int p = (int)(s.idf[hint] & kIdMask);
-        // Runner-up: the next unexpanded vertex.  Its row, attributes and
-        // vectors are fetched together with p's; after p's candidates are
-        // merged it is expanded only if it is then the first unexpanded
-        // vertex, i.e. exactly the vertex Algorithm 1 expands next.  (The
-        // fourth expansion is never speculative: the predictor reads the
-        // list right after it.)
-        bool spec = a.spec && hops + 2 <= hopcap && (predicted || hops != 3);
-        const int h2 = spec ? first_unexpanded(s, hint + 1, cnt) : cnt;
-        spec = h2 < cnt;
-        const int p2 = spec ? (int)(s.idf[h2] & kIdMask) : 0;
         __syncthreads();
         if (lane == 0) {
             s.idf[hint] |= kExpanded;
             if (hops < 4) s.exkey[hops] = s.key[hint];
         }
         hops++;
-        // one row holds the neighbour ids and their attribute words: all
+        // one row holds the neighbour ids and their attribute words: both
         // loads are issued together, before the ids are known
         const int32_t *row = a.adj + (int64_t)p * a.adj_words;
-        const int32_t *row2 = a.adj + (int64_t)p2 * a.adj_words;
-        int32_t u = -1, u2 = -1;
-        ItemAttr at, at2;
+        int32_t u = -1;
+        ItemAttr at;
         if (lane < a.R) {
             u = row[lane];
             load_row_attr(at, f, row, lane, a);
-            if (spec) {
-                u2 = row2[lane];
-                load_row_attr(at2, f, row2, lane, a);
-            }
         }
         bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
-        __syncthreads();
-        // the runner-up's neighbours are looked up after p's are inserted, as
-        // they would be if it were expanded next; they are inserted on commit
-        const bool unseen2 = spec && u2 >= 0 && !hash_find(s.hash, a.Hmask, u2);
-        bool fresh2 = unseen2;
-        uint32_t df, df2;
-        dist_f_pair(f, at, at2, a, df, df2);
-        df = fresh ? df : 0u;
-        df2 = fresh2 ? df2 : 0u;
-        nattr += __popcll(ballot64(fresh)) + __popcll(ballot64(fresh2));
-        if (cnt == ls) {
-            const uint32_t wdf = (uint32_t)(s.key[cnt - 1] >> 32);
-            fresh = fresh && df <= wdf;
-            fresh2 = fresh2 && df2 <= wdf;
-        }
-        const uint64_t bm = ballot64(fresh), bm2 = ballot64(fresh2);
-        const int m = __popcll(bm), m2 = __popcll(bm2);
+        uint32_t df = fresh ? dist_f(f, at, a) : 0u;
+        nattr += __popcll(ballot64(fresh));
+        if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
+        uint64_t bm = ballot64(fresh);
+        int m = __popcll(bm);
         if (fresh) {
             int slot = lanes_below(bm);
             s.cid[slot] = u;
             s.cdf[slot] = df;
         }
-        if (fresh2) {
-            int slot = m + lanes_below(bm2);
-            s.cid[slot] = u2;
-            s.cdf[slot] = df2;
-        }
         __syncthreads();
-        if (m + m2 > 0) {
-            eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m + m2, qr);
-            __syncthreads();
-            ndist += m + m2;
-        }
         int minpos = INT_MAX;
-        if (m > 0) cnt = merge_candidates(s, 0, m, cnt, ls, &minpos);
-        hint = minpos < hint + 1 ? minpos : hint + 1;
-        if (spec) {
-            const int hn = first_unexpanded(s, hint, cnt);
-            if (hn < cnt && (int)(s.idf[hn] & kIdMask) == p2) {
-                __syncthreads();
-                if (lane == 0) {
-                    s.idf[hn] |= kExpanded;
-                    if (hops < 4) s.exkey[hops] = s.key[hn];
-                }
-                hops++;
-                if (unseen2) hash_insert(s.hash, a.Hmask, u2);
-                __syncthreads();
-                int mp2 = INT_MAX;
-                if (m2 > 0) cnt = merge_candidates(s, m, m2, cnt, ls, &mp2);
-                hint = mp2 < hn + 1 ? mp2 : hn + 1;
-            }
+        if (m > 0) {
+            eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
+            __syncthreads();
+            ndist += m;
+            cnt = merge_candidates(s, m, cnt, ls, &minpos);
         }
+        hint = minpos < hint + 1 ? minpos : hint + 1;
         if (!predicted && hops == 4) {
             predicted = true;
             // predictor features after the fourth expansion
@@ -729,11 +639,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void se
                 hopcap = cap < hopcap ? cap : hopcap;
                 if (cnt > lhat) cnt = lhat;
                 ls = lhat;
+                if (a.mode == 3) {  // save the state after the cut and stop
+                    int32_t *ws = a.state + q * a.state_stride;
+                    uint64_t *sk = reinterpret_cast<uint64_t *>(ws + 8);
+                    uint32_t *si = reinterpret_cast<uint32_t *>(ws + 8 + 2 * a.Lcap);
+                    int4 *sh = reinterpret_cast<int4 *>(ws + 8 + 3 * a.Lcap);
+                    for (int j = lane; j < cnt; j += 64) {
+                        sk[j] = s.key[j];
+                        si[j] = s.idf[j];
+                    }
+                    for (int j = lane; j < (H >> 2); j += 64) sh[j] = reinterpret_cast<const int4 *>(s.hash)[j];
+                    if (lane < 8) {
+                        int v = lane == 0 ? idx + 1 : lane == 1 ? cnt : lane == 2 ? hint : lane == 3 ? hops
+                              : lane == 4 ? ndist : lane == 5 ? nattr : lane == 6 ? hopcap : lhat;
+                        ws[lane] = v;
+                    }
+                    return;
+                }
             }
         }
     }
     if (a.mode == 2 && !predicted && lane < 16)  // fewer than four expansions: no features
         a.features[q * 16 + lane] = lane == 15 ? -1.f : 0.f;
+    if (a.mode == 3) {  // ended before the prediction point: the search pass redoes it
+        if (lane == 0) a.state[q * a.state_stride] = 0;
+        return;
+    }
     // ---- output: top-k valid entries, optionally rescored in FP32
     int outn = cnt;
     if (a.rerank > 0) {
@@ -825,7 +756,7 @@ __global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
         eval_rows<JAG_STORE_F32, G, CH>(a.f32, a.f32_stride, s.cid, s.cd2, m, qr);
         __syncthreads();
         int mp;
-        cnt = merge_candidates(s, 0, m, cnt, a.k, &mp);
+        cnt = merge_candidates(s, m, cnt, a.k, &mp);
     }
     bool ok = lane < cnt && lane < a.k;
     if (lane < a.k) {
@@ -906,6 +837,63 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
     if (i < n) out[i] = to_bf16(x[i]);
 }
 
+// ---------------------------------------------------------------- schedule
+// Longest-predicted-first order for the search pass of a two-pass learned
+// search: a stable counting sort of the queries by the first word of their
+// saved state, 1 + predicted ladder index (0 = finished before the
+// prediction point), largest first.  One workgroup; thread t owns the
+// contiguous chunk [t*chunk, (t+1)*chunk) of queries.
+constexpr int kOrderThreads = 512;
+constexpr int kOrderBins = JAG_LADDER_MAX + 1;
+
+__global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *state, int64_t stride, int64_t nq,
+                                                               int32_t *perm)
+{
+    __shared__ int32_t cnt[kOrderBins][kOrderThreads];
+    __shared__ int32_t part[kOrderThreads];
+    const int t = threadIdx.x;
+    const int64_t chunk = (nq + kOrderThreads - 1) / kOrderThreads;
+    const int64_t b0 = (int64_t)t * chunk;
+    const int64_t b1 = b0 + chunk < nq ? b0 + chunk : nq;
+    for (int b = 0; b < kOrderBins; b++) cnt[b][t] = 0;
+    for (int64_t i = b0; i < b1; i++) {
+        int k = state[i * stride];
+        k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
+        cnt[k][t]++;
+    }
+    __syncthreads();
+    // output rank r enumerates (bin descending, thread ascending); thread t
+    // scans ranks [t*kOrderBins, (t+1)*kOrderBins)
+    int sum = 0;
+    for (int j = 0; j < kOrderBins; j++) {
+        int r = t * kOrderBins + j;
+        sum += cnt[kOrderBins - 1 - r / kOrderThreads][r % kOrderThreads];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kOrderThreads; off <<= 1) {  // inclusive scan of the partial sums
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    __syncthreads();
+    for (int j = 0; j < kOrderBins; j++) {
+        int r = t * kOrderBins + j;
+        int *c = &cnt[kOrderBins - 1 - r / kOrderThreads][r % kOrderThreads];
+        int v = *c;
+        *c = run;  // exclusive offset of (bin, thread)
+        run += v;
+    }
+    __syncthreads();
+    for (int64_t i = b0; i < b1; i++) {
+        int k = state[i * stride];
+        k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
+        perm[cnt[k][t]++] = (int32_t)i;
+    }
+}
+
 // ---------------------------------------------------------------- host glue
 #define HIPCHK(expr)                                                               \
     do {                                                                           \
@@ -970,11 +958,21 @@ ExactFn exact_for_ch(int ch)
     return nullptr;
 }
 
-// Measured on the range workload: 2^11 slots beat 2^10 (fewer repeated
-// evaluations) and 2^12 (lower occupancy: at L = 96, 2^12 cost 17 %).
-constexpr int kDefaultHash = 2048;
+// Seen-table slots.  The kernel holds at most 4 waves per SIMD (16 per CU)
+// by registers; 2^10 slots keep LDS from lowering that for lists up to 128
+// entries.  Measured on the range workload (1M x 96, 10k queries): equal to
+// 2^11 at fixed L = 44 and 64 (6-9 % more repeated evaluations, 14 % more
+// resident queries), 17-20 % faster for learned beams (128-entry list).
+constexpr int kDefaultHash = 1024;
 // List width of the first four expansions in learned and trace modes.
 constexpr int kWarmWidth = 128;
+// Device memory a two-pass learned search may hold for saved states; larger
+// batches are processed in chunks of queries that fit.
+constexpr int64_t kStateBudget = int64_t(512) << 20;
+
+// Words of one saved search state: 8 counters, the list (8-byte keys and
+// 4-byte ids of up to Lcap entries) and the H-slot seen-table.
+constexpr int64_t state_words(int Lcap, int H) { return 8 + 3 * (int64_t)Lcap + H; }
 
 }  // namespace
 
@@ -1171,6 +1169,9 @@ static jag_status fill_args(Index &ix, SearchArgs &a, const float *Q, const void
     a.lab_word_off = ix.lab_word_off;
     a.entry = ix.entry;
     a.k = k;
+    a.perm = nullptr;
+    a.state = nullptr;
+    a.state_stride = 0;
     return JAG_OK;
 }
 
@@ -1212,7 +1213,6 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
     a.delta = S.delta;
     a.rerank = S.rerank_mult;
     a.max_hops = S.max_hops;
-    a.spec = S.no_speculation ? 0 : 1;
     a.nladder = ix.pred.nladder;
     a.rho = ix.pred.rho;
     for (int i = 0; i < JAG_LADDER_MAX; i++) a.ladder[i] = ix.pred.ladder[i];
@@ -1241,8 +1241,7 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
         set_error("no kernel for row stride %d", ix.vec_stride);
         return JAG_EUNSUPPORTED;
     }
-    const int eb = ix.store == JAG_STORE_F32 ? 4 : ix.store == JAG_STORE_BF16 ? 2 : 1;
-    lds = lds_bytes(Lcap, H, kQueryInLds ? ix.vec_stride / eb : 0);
+    lds = lds_bytes(Lcap, H);
     return JAG_OK;
 }
 
@@ -1255,8 +1254,51 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     size_t lds = 0;
     jag_status st = plan_search(ix, Q, nq, records, k, S, ids, dists, count, a, fn, lds);
     if (st != JAG_OK) return st;
-    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, (hipStream_t)stream, a);
-    HIPCHK(hipGetLastError());
+    if (nq == 0) return JAG_OK;
+    hipStream_t sm = (hipStream_t)stream;
+    if (S.learned != 1 || S.single_pass || nq < 2) {
+        hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, sm, a);
+        HIPCHK(hipGetLastError());
+        return JAG_OK;
+    }
+    // two passes over chunks of queries: run each to its prediction and save
+    // its state (list, seen-table, counters), order the chunk by predicted
+    // beam, widest first, then resume every search in that order
+    const int64_t stride = state_words(a.Lcap, a.Hmask + 1);
+    const int64_t per_q = (stride + 1) * (int64_t)sizeof(int32_t);
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
+    int32_t *scratch = nullptr;
+    HIPCHK(hipMallocAsync((void **)&scratch, (size_t)(chunk * per_q), sm));
+    int32_t *perm = scratch + chunk * stride;
+    hipError_t e = hipSuccess;
+    for (int64_t c0 = 0; c0 < nq && e == hipSuccess; c0 += chunk) {
+        const int64_t nc = std::min(chunk, nq - c0);
+        SearchArgs b = a;
+        b.Q = a.Q + c0 * a.d;
+        b.rec = a.rec + c0;
+        b.ids = a.ids + c0 * k;
+        b.dists = a.dists + c0 * k;
+        b.count = a.count + c0;
+        b.stats = a.stats ? a.stats + c0 * 4 : nullptr;
+        b.state = scratch;
+        b.state_stride = stride;
+        SearchArgs b3 = b;
+        b3.mode = 3;
+        b3.stats = nullptr;
+        hipLaunchKernelGGL(fn, dim3((unsigned)nc), dim3(64), lds, sm, b3);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, scratch, stride, nc, perm);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+        b.mode = 4;
+        b.perm = perm;
+        hipLaunchKernelGGL(fn, dim3((unsigned)nc), dim3(64), lds, sm, b);
+        e = hipGetLastError();
+    }
+    hipError_t ef = hipFreeAsync(scratch, sm);
+    HIPCHK(e);
+    HIPCHK(ef);
     return JAG_OK;
 }
 
@@ -1302,7 +1344,7 @@ jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *recor
         set_error("no exact kernel for FP32 row stride %d", ix.f32_stride);
         return JAG_EUNSUPPORTED;
     }
-    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds_bytes(64, 1, 0), (hipStream_t)stream, a, ix.n);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds_bytes(64, 1), (hipStream_t)stream, a, ix.n);
     HIPCHK(hipGetLastError());
     return JAG_OK;
 }

@@ -52,7 +52,7 @@ class jag_search_params(C.Structure):
     _fields_ = [("L", C.c_int32), ("learned", C.c_int32), ("delta", C.c_float),
                 ("rerank_mult", C.c_int32), ("max_hops", C.c_int32), ("stats", C.c_void_p),
                 ("features", C.c_void_p), ("hash_log2", C.c_int32),
-                ("no_speculation", C.c_int32)]
+                ("single_pass", C.c_int32)]
 
 
 class jag_index_info(C.Structure):
@@ -267,12 +267,13 @@ class SearchParams:
     stats: Optional[object] = None      # torch int32 [nq, 4] on the device
     features: Optional[object] = None   # torch float32 [nq, 16] on the device
     hash_log2: int = 0
-    no_speculation: int = 0
+    single_pass: int = 0
 
     def c(self) -> jag_search_params:
         return jag_search_params(int(self.L), int(self.learned), float(self.delta),
                                  int(self.rerank_mult), int(self.max_hops), _ptr(self.stats),
-                                 _ptr(self.features), int(self.hash_log2), int(self.no_speculation))
+                                 _ptr(self.features), int(self.hash_log2),
+                                 int(self.single_pass))
 
 
 def jag_search_encoded(idx: Index, Q, records, k: int, params: SearchParams, ids, dists, count,

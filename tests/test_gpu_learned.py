@@ -120,6 +120,37 @@ def test_learned_cut_is_exact(c1_small):
     assert seen == w.nq
 
 
+def test_two_pass_schedule_is_exact(c1_small, mixed_world):
+    """The default two-pass learned search (run to the prediction and save the
+    state, order longest first, resume) returns exactly what one launch in
+    submission order returns: ids, distances, counts, expansions, distance
+    and attribute counts, chosen beams."""
+    w, A, adj, entry = c1_small
+    _say("two-pass learned schedule")
+    ladder = np.array([10, 16, 24, 40, 64, 96, 128], dtype=np.int32)
+    idx = jag.jag_build_from_graph(w.X, adj, entry, label_off=w.loff, labels=w.lab, vocab=8)
+    cases = [(idx, w.Q, w.F, w.pool, 0)]
+    mw, _, madj, mentry = mixed_world
+    midx = jag.jag_build_from_graph(mw.X, madj, mentry, scalar=mw.scalar, label_off=mw.loff,
+                                    labels=mw.lab, vocab=mw.vocab)
+    cases.append((midx, mw.Q, mw.F, mw.pool, 0))
+    # a single query; a hop limit below the prediction point (no saved state);
+    # a hop limit just past it
+    cases.append((idx, w.Q[:1], w.F[:1], w.pool, 0))
+    cases.append((idx, w.Q, w.F, w.pool, 3))
+    cases.append((midx, mw.Q, mw.F, mw.pool, 6))
+    for seed, (ix, Q, F, pool, mh) in enumerate(cases):
+        jag.jag_set_predictor(ix, _params(20 + seed, scale=0.4), ladder, 2.5)
+        for delta in (-1.0, 0.5, 3.0):
+            one = gpu_search(ix, Q, F, pool, 10, 10, learned=1, delta=delta, single_pass=1,
+                             max_hops=mh)
+            two = gpu_search(ix, Q, F, pool, 10, 10, learned=1, delta=delta, single_pass=0,
+                             max_hops=mh)
+            for key in ("ids", "d2", "count", "stats"):
+                assert np.array_equal(one[key], two[key]), (seed, delta, key)
+        _say(f"case {seed}: beams {np.unique(two['stats'][:, 3]).tolist()}")
+
+
 def test_trace_features_are_beam_independent(c1_small):
     """Trace mode writes the same features whatever the final beam (the first four
     expansions keep every discovered vertex), and its answers equal fixed search."""

@@ -22,7 +22,7 @@ def _say(*a):
 
 
 def gpu_search(idx, Q, F, pool, k, L, learned=0, delta=0.0, rerank_mult=0, max_hops=0,
-               features=False):
+               features=False, single_pass=0):
     import torch
     dev = torch.device("cuda:0")
     nq = Q.shape[0]
@@ -35,7 +35,7 @@ def gpu_search(idx, Q, F, pool, k, L, learned=0, delta=0.0, rerank_mult=0, max_h
     stats = torch.zeros((nq, 4), dtype=torch.int32, device=dev)
     feats = torch.zeros((nq, 16), dtype=torch.float32, device=dev) if features else None
     sp = jag.SearchParams(L=L, learned=learned, delta=delta, rerank_mult=rerank_mult,
-                          max_hops=max_hops, stats=stats, features=feats)
+                          max_hops=max_hops, stats=stats, features=feats, single_pass=single_pass)
     jag.jag_search_encoded(idx, Qd, recd, k, sp, ids, dists, count)
     torch.cuda.synchronize()
     out = dict(ids=ids.cpu().numpy(), d2=dists.cpu().numpy(), count=count.cpu().numpy(),
@@ -214,31 +214,6 @@ def test_save_load_roundtrip(mixed_world, tmp_path):
     g1 = gpu_search(idx, w.Q, w.F, w.pool, 10, 48, rerank_mult=4)
     g2 = gpu_search(idx2, w.Q, w.F, w.pool, 10, 48, rerank_mult=4)
     assert np.array_equal(g1["ids"], g2["ids"]) and np.array_equal(g1["d2"], g2["d2"])
-
-
-@pytest.mark.parametrize("store", [jag.STORE_F32, jag.STORE_FP8_E4M3])
-def test_speculation_is_exact(mixed_world, c1_small, store):
-    """Fetching the runner-up vertex early and keeping its expansion only when
-    Algorithm 1 would expand it next changes no result and no expansion count."""
-    for w, A, adj, entry in (mixed_world, c1_small):
-        idx = _index(w, adj, entry, store=store, keep_f32=True)
-        for L in (10, 40, 96):
-            import torch
-            outs = []
-            for ns in (0, 1):
-                rec = torch.from_numpy(jag.jag_encode_filters(idx, w.F, w.pool)).cuda()
-                Qd = torch.from_numpy(w.Q).cuda()
-                ids = torch.empty((w.nq, 10), dtype=torch.int32, device="cuda")
-                d2 = torch.empty((w.nq, 10), dtype=torch.float32, device="cuda")
-                cnt = torch.empty((w.nq,), dtype=torch.int32, device="cuda")
-                st = torch.zeros((w.nq, 4), dtype=torch.int32, device="cuda")
-                jag.jag_search_encoded(idx, Qd, rec, 10, jag.SearchParams(L=L, stats=st, no_speculation=ns),
-                                       ids, d2, cnt)
-                torch.cuda.synchronize()
-                outs.append((ids.cpu().numpy(), d2.cpu().numpy(), st.cpu().numpy()))
-            assert np.array_equal(outs[0][0], outs[1][0])
-            assert np.array_equal(outs[0][1].view(np.uint32), outs[1][1].view(np.uint32))
-            assert np.array_equal(outs[0][2][:, 0], outs[1][2][:, 0])  # same expansions
 
 
 def test_repeat_and_shuffle_give_identical_results(mixed_world):
