@@ -146,8 +146,12 @@ typedef struct {
                             decreasing predicted beam (longest first, so the batch
                             does not end on a few long searches), reusing the recorded
                             beams; 1 = one launch in submission order.  Results are
-                            identical; two passes need 8*nq bytes of stream-ordered
-                            scratch. */
+                            identical.  Two passes allocate stream-ordered device
+                            scratch (hipMallocAsync on the call's stream) for each
+                            query's saved state: (8 + 3*W + S + 1) * 4 bytes, W = list
+                            width (128 or the widest beam, rounded up to 64), S =
+                            seen-table slots (5.7 KB at W = 128, S = 1024); batches
+                            needing more than 512 MiB run in chunks. */
 } jag_search_params;
 
 typedef struct {
@@ -315,7 +319,9 @@ typedef struct {
     int32_t max_wait_us;      /* a partial batch waits at most this long for company */
     int64_t max_inflight;     /* 0 = resident capacity of the device for this search */
     int64_t queue_capacity;   /* pending requests beyond this are refused (JAG_EBUSY) */
-    int64_t hbm_budget_bytes; /* 0 = no limit; else the server's device buffers must fit */
+    int64_t hbm_budget_bytes; /* 0 = no limit; else the server's device buffers (per stream:
+                                 a batch's queries, records and results, plus the saved
+                                 states of a two-pass learned search) must fit */
 } jag_server_params;
 
 typedef struct {

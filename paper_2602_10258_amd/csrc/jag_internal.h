@@ -118,6 +118,10 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
 // Query wavefronts of this search the device can hold resident at once.
 jag_status search_capacity(Index &ix, int32_t k, const jag_search_params &S, int64_t *resident,
                            size_t *lds_per_query);
+// Stream-ordered device scratch one launch_search of nq queries allocates
+// (the saved states of a two-pass learned search; 0 otherwise).
+jag_status search_scratch_bytes(Index &ix, int32_t k, const jag_search_params &S, int64_t nq,
+                                int64_t *bytes);
 jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
                         int32_t *ids, float *dists, int32_t *count, void *stream);
 jag_status upload_predictor(Index &ix);

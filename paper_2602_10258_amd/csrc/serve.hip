@@ -256,7 +256,10 @@ jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_serv
     size_t lds = 0;
     jag_status st = jag::search_capacity(ix, P->k, P->search, &resident, &lds);
     if (st != JAG_OK) return st;
-    int64_t dev_bytes = (int64_t)P->n_streams * slot_device_bytes(P->max_batch, ix.d, P->k);
+    int64_t scratch = 0;  // two-pass learned search: saved states of one batch
+    st = jag::search_scratch_bytes(ix, P->k, P->search, P->max_batch, &scratch);
+    if (st != JAG_OK) return st;
+    int64_t dev_bytes = (int64_t)P->n_streams * (slot_device_bytes(P->max_batch, ix.d, P->k) + scratch);
     if (P->hbm_budget_bytes > 0 && dev_bytes > P->hbm_budget_bytes) {
         set_error("server buffers need %lld bytes, over the %lld-byte budget", (long long)dev_bytes,
                   (long long)P->hbm_budget_bytes);
