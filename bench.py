@@ -18,6 +18,7 @@ whole query batch, inputs resident in HBM.  One JSON line on stdout.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -60,6 +61,8 @@ def parse():
     ap.add_argument("--rates", default="5000,20000,50000,100000,200000")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="profile mode: also run device copies of this many bytes")
+    ap.add_argument("--filter-type", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--graph-cache", default=None,
                     help="load the graph from this .npz if present, else build and save it there")
     return ap.parse_args()
@@ -88,11 +91,15 @@ class Timer:
         return float(np.median(times))
 
 
+FILTER_NAMES = {0: "label", 1: "range", 2: "subset", 3: "boolean"}
+
+# (attribute kind, quantile) lists: 0 scalar, 1 labels |a XOR b|, 2 labels with
+# the frequency-weighted distance the paper uses for skewed label vocabularies
 THRESHOLDS = {
     "c1": [(1, 1.0), (1, 0.0)],
     "c2": [(0, 1.0), (0, 0.01), (0, 0.0)],
-    "c3": [(1, 1.0), (1, 0.01), (1, 0.0)],
-    "c5": [(0, 1.0), (0, 0.01), (0, 0.0), (1, 0.01), (1, 0.0)],
+    "c3": [(2, 1.0), (2, 0.01), (2, 0.0)],
+    "c5": [(0, 1.0), (0, 0.01), (0, 0.0), (2, 0.01), (2, 0.0)],
 }
 
 
@@ -232,6 +239,10 @@ def main():
     dev = torch.device("cuda:0")
     t0 = time.time()
     w = make_config(args.config, n=args.n, nq=args.nq)
+    if args.filter_type is not None:
+        keep = w.F[:, 0] == args.filter_type
+        assert keep.any(), f"no queries of filter type {args.filter_type} in {w.name}"
+        w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
     k = w.k
     log(f"workload {w.name}: n={w.n} d={w.d} nq={w.nq} ({time.time() - t0:.1f}s)")
 
@@ -443,6 +454,7 @@ def main():
         "config": {"workload": f"{w.name}: {w.n} x {w.d} clustered vectors, {nq} queries "
                                f"({w.meta.get('thresholds')}), k={k}, R={w.R}",
                    "global_batch": nq, "mode": op["mode"], "recall_at_10": round(rec_final, 4),
+                   "filter_types": sorted({FILTER_NAMES[int(t)] for t in w.F[:, 0]}),
                    "storage": "bf16 (+fp32 rerank)" if op["rerank"] else "fp32"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},

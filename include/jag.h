@@ -66,8 +66,12 @@ typedef enum {
     JAG_BOOLEAN = 3  /* DNF program in pool[off, off+len): see jag_filter */
 } jag_filter_type;
 
-/* Attribute kinds an index can hold; the threshold list names one per entry. */
-typedef enum { JAG_ATTR_SCALAR = 0, JAG_ATTR_LABELS = 1 } jag_attr_kind;
+/* Attribute distances dist_A the threshold list can name, one per entry
+ * (Section 3.1): SCALAR |a1 - a2|; LABELS |a1 XOR a2|; LABELS_WEIGHTED the
+ * frequency-weighted label distance of App. D.3, C - sum over shared labels l
+ * of log(1/p_l), p_l = fraction of items holding l, C = the largest total
+ * weight of one item's labels (meant for large, skewed label vocabularies). */
+typedef enum { JAG_ATTR_SCALAR = 0, JAG_ATTR_LABELS = 1, JAG_ATTR_LABELS_WEIGHTED = 2 } jag_attr_kind;
 
 /* Per-item attributes (host).  Either part may be absent (NULL). */
 typedef struct {

@@ -38,6 +38,7 @@
 
 #define OR_KIND_SCALAR 0
 #define OR_KIND_LABELS 1
+#define OR_KIND_LABELS_WEIGHTED 2
 
 /* dist_F of an item against a filter that no attribute can satisfy */
 #define OR_UNSAT 4294967295.0
@@ -47,6 +48,8 @@ typedef struct {
     const int32_t *scalar; /* [n] or NULL */
     const int64_t *loff;   /* [n+1] or NULL */
     const int32_t *lab;    /* label sets, each row sorted */
+    const double *lw;      /* per-label weight log(1/p_l), for OR_KIND_LABELS_WEIGHTED */
+    double lw_c;           /* the constant C of the weighted distance */
 } or_attrs;
 
 typedef struct {
@@ -125,10 +128,44 @@ static double dist_f(const or_attrs *A, int64_t i, const or_filter *f, const int
     return OR_UNSAT;
 }
 
-/* dist_A: |a1 - a2| for scalars; |a1 XOR a2| (symmetric difference) for label sets. */
+/*
+ * Label weights of the frequency-weighted label distance (App. D.3, the
+ * variant the paper uses for label-heavy datasets): p_l = fraction of items
+ * holding label l, weight log(1/p_l); C = the largest total weight of one
+ * item's labels, so that C - (weight of any shared set) >= 0.  Returns a
+ * malloc'd array indexed by label (0 for labels nobody holds).
+ */
+static double *label_weights(const or_attrs *A, double *c_out)
+{
+    int32_t vocab = 0;
+    for (int64_t x = 0; x < A->loff[A->n]; x++)
+        if (A->lab[x] + 1 > vocab) vocab = A->lab[x] + 1;
+    double *cnt = calloc((size_t)(vocab > 0 ? vocab : 1), sizeof(double));
+    for (int64_t x = 0; x < A->loff[A->n]; x++) cnt[A->lab[x]] += 1.0;
+    for (int32_t l = 0; l < vocab; l++) cnt[l] = cnt[l] > 0.0 ? log((double)A->n / cnt[l]) : 0.0;
+    double c = 0.0;
+    for (int64_t i = 0; i < A->n; i++) {
+        double t = 0.0;
+        for (int64_t x = A->loff[i]; x < A->loff[i + 1]; x++) t += cnt[A->lab[x]];
+        if (t > c) c = t;
+    }
+    *c_out = c;
+    return cnt;
+}
+
+/*
+ * dist_A: |a1 - a2| for scalars; |a1 XOR a2| (symmetric difference) for label
+ * sets; C - sum of log(1/p_l) over shared labels l for weighted label sets.
+ */
 static double dist_a(const or_attrs *A, int kind, int64_t i, int64_t j)
 {
     if (kind == OR_KIND_SCALAR) return fabs((double)A->scalar[i] - (double)A->scalar[j]);
+    if (kind == OR_KIND_LABELS_WEIGHTED) {
+        double shared = 0.0;
+        for (int64_t x = A->loff[i]; x < A->loff[i + 1]; x++)
+            if (item_has(A, j, A->lab[x])) shared += A->lw[A->lab[x]];
+        return A->lw_c - shared;
+    }
     double common = 0.0;
     for (int64_t x = A->loff[i]; x < A->loff[i + 1]; x++)
         if (item_has(A, j, A->lab[x])) common += 1.0;
@@ -535,7 +572,7 @@ int or_search(int64_t n, int32_t d, const float *base, const int32_t *adj, int32
     for (int32_t t = 0; t < nthreads; t++) {
         search_job *J = &jobs[t];
         J->G = (or_graph){adj, R, n, entry, base, d};
-        J->A = (or_attrs){n, scalar, loff, lab};
+        J->A = (or_attrs){n, scalar, loff, lab, NULL, 0.0};
         J->Q = Q;
         J->F = (const or_filter *)F;
         J->pool = pool;
@@ -634,7 +671,7 @@ void or_dist_f_pairs(int64_t n, const int32_t *scalar, const int64_t *loff, cons
                      int64_t m, const int64_t *items, const int32_t *F, const int32_t *fidx,
                      const int32_t *pool, double *out)
 {
-    or_attrs A = {n, scalar, loff, lab};
+    or_attrs A = {n, scalar, loff, lab, NULL, 0.0};
     for (int64_t j = 0; j < m; j++)
         out[j] = dist_f(&A, items[j], (const or_filter *)F + fidx[j], pool);
 }
@@ -643,8 +680,11 @@ void or_dist_a_pairs(int64_t n, const int32_t *scalar, const int64_t *loff, cons
                      int32_t kind, int64_t m, const int64_t *i1, const int64_t *i2, double t,
                      double *out)
 {
-    or_attrs A = {n, scalar, loff, lab};
+    or_attrs A = {n, scalar, loff, lab, NULL, 0.0};
+    double *lw = NULL;
+    if (kind == OR_KIND_LABELS_WEIGHTED) A.lw = lw = label_weights(&A, &A.lw_c);
     for (int64_t j = 0; j < m; j++) out[j] = dist_a_capped(&A, kind, i1[j], i2[j], t);
+    free(lw);
 }
 
 /* ------------------------------------------------------------------ */
@@ -877,7 +917,10 @@ int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     B.nT = nT;
     B.alpha = alpha;
     B.X = X;
-    B.A = (or_attrs){n, scalar, loff, lab};
+    B.A = (or_attrs){n, scalar, loff, lab, NULL, 0.0};
+    double *lw = NULL;
+    for (int32_t ti = 0; ti < nT; ti++)
+        if (kinds[ti] == OR_KIND_LABELS_WEIGHTED && !lw) B.A.lw = lw = label_weights(&B.A, &B.A.lw_c);
     B.kinds = kinds;
     B.thr = malloc(sizeof(double) * (size_t)n * (size_t)nT);
     B.adj = adj;
@@ -931,6 +974,7 @@ int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     free(order);
     free(B.thr);
     free(B.deg);
+    free(lw);
     return s;
 }
 
@@ -1116,8 +1160,13 @@ int32_t or_prune(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     B.nT = nT;
     B.alpha = alpha;
     B.X = X;
-    B.A = (or_attrs){n, scalar, loff, lab};
+    B.A = (or_attrs){n, scalar, loff, lab, NULL, 0.0};
+    double *lw = NULL;
+    for (int32_t ti = 0; ti < nT; ti++)
+        if (kinds[ti] == OR_KIND_LABELS_WEIGHTED && !lw) B.A.lw = lw = label_weights(&B.A, &B.A.lw_c);
     B.kinds = kinds;
     B.thr = (double *)thr;
-    return joint_robust_prune(&B, p, cand, ncand, out);
+    int32_t m = joint_robust_prune(&B, p, cand, ncand, out);
+    free(lw);
+    return m;
 }

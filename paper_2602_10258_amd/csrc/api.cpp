@@ -339,11 +339,11 @@ static jag_status make_config(const float *X, int64_t n, int32_t d, const jag_at
             set_error("threshold %d names scalar attributes the index does not have", i);
             return JAG_EINVAL;
         }
-        if (kind == JAG_ATTR_LABELS && !(A && A->label_off)) {
+        if ((kind == JAG_ATTR_LABELS || kind == JAG_ATTR_LABELS_WEIGHTED) && !(A && A->label_off)) {
             set_error("threshold %d names labels the index does not have", i);
             return JAG_EINVAL;
         }
-        if (kind != JAG_ATTR_SCALAR && kind != JAG_ATTR_LABELS) {
+        if (kind != JAG_ATTR_SCALAR && kind != JAG_ATTR_LABELS && kind != JAG_ATTR_LABELS_WEIGHTED) {
             set_error("threshold %d: unknown attribute kind %d", i, kind);
             return JAG_EINVAL;
         }

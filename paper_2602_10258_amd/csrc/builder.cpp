@@ -89,10 +89,26 @@ struct Builder {
     std::vector<float> thr;  // [n][nT]
     std::vector<int32_t> adj;
     std::vector<int32_t> deg;
+    std::vector<float> lw;  // weighted labels: log(1/p_l) per label
+    float lw_c = 0.f;       // and the constant C
 
     float dist_a(int kind, int64_t i, int64_t j) const
     {
         if (kind == JAG_ATTR_SCALAR) return std::fabs((float)((int64_t)A.scalar[i] - (int64_t)A.scalar[j]));
+        if (kind == JAG_ATTR_LABELS_WEIGHTED) {
+            // C minus the weight of the shared labels (merge of the sorted rows)
+            int64_t x = A.loff[i], xe = A.loff[i + 1], y = A.loff[j], ye = A.loff[j + 1];
+            float shared = 0.f;
+            while (x < xe && y < ye) {
+                if (A.lab[x] == A.lab[y]) {
+                    shared += lw[A.lab[x]];
+                    x++;
+                    y++;
+                } else if (A.lab[x] < A.lab[y]) x++;
+                else y++;
+            }
+            return lw_c - shared;
+        }
         // |a_i XOR a_j| by merging the two sorted rows
         int64_t x = A.loff[i], xe = A.loff[i + 1], y = A.loff[j], ye = A.loff[j + 1];
         int64_t common = 0;
@@ -253,6 +269,24 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
     B.alpha2 = cfg.alpha * cfg.alpha;
     B.kinds = cfg.kinds;
     int nth = cfg.n_threads > 0 ? cfg.n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    if (std::find(B.kinds.begin(), B.kinds.end(), (int32_t)JAG_ATTR_LABELS_WEIGHTED) != B.kinds.end()) {
+        // frequency-weighted label distance (App. D.3): weight log(1/p_l),
+        // p_l = fraction of items holding l; C = the largest item total
+        int32_t vocab = 1;
+        for (int64_t x = 0; x < A.loff[n]; x++) vocab = std::max(vocab, A.lab[x] + 1);
+        std::vector<double> cnt((size_t)vocab, 0.0);
+        for (int64_t x = 0; x < A.loff[n]; x++) cnt[(size_t)A.lab[x]] += 1.0;
+        B.lw.assign(cnt.size(), 0.f);
+        for (size_t l = 0; l < cnt.size(); l++)
+            B.lw[l] = cnt[l] > 0.0 ? (float)std::log((double)n / cnt[l]) : 0.f;
+        double c = 0.0;
+        for (int64_t i = 0; i < n; i++) {
+            double t = 0.0;
+            for (int64_t x = A.loff[i]; x < A.loff[i + 1]; x++) t += B.lw[(size_t)A.lab[x]];
+            c = std::max(c, t);
+        }
+        B.lw_c = (float)c;
+    }
 
     // entry vertex: nearest to the FP64 centroid, smaller id on ties
     std::vector<double> cen(d, 0.0);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libjag.so")
 JAG_OK, JAG_EINVAL, JAG_ENOMEM, JAG_EDEVICE, JAG_EIO, JAG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 STORE_F32, STORE_BF16, STORE_FP8_E4M3 = 0, 1, 2
 LABEL, RANGE, SUBSET, BOOLEAN = 0, 1, 2, 3
-ATTR_SCALAR, ATTR_LABELS = 0, 1
+ATTR_SCALAR, ATTR_LABELS, ATTR_LABELS_WEIGHTED = 0, 1, 2
 FILTER_RECORD_BYTES = 128
 LADDER_MAX = 16
 N_PARAMS = 5313

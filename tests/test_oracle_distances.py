@@ -198,3 +198,27 @@ def test_range_capped_dist_is_range_filter_distance():
         df = O.dist_f(A, np.arange(n), F, np.zeros(n, dtype=np.int32), pool)
         da = O.dist_a(A, O.KIND_SCALAR, np.full(n, p), np.arange(n), float(t))
         assert np.array_equal(df, da)
+
+
+def test_weighted_label_distance_hand_worked():
+    """Frequency-weighted label distance (App. D.3) on a five-item example
+    worked by hand (tests/golden/dist_a_weighted_examples.txt)."""
+    A = _attrs_from_sets([{0}, {0, 1}, {0, 2}, {0, 1, 2}, {3}])
+    rows = []
+    with open(os.path.join(HERE, "golden", "dist_a_weighted_examples.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                u, v, val = line.split()
+                rows.append((int(u), int(v), float(val)))
+    assert len(rows) == 6
+    u = np.array([r[0] for r in rows])
+    v = np.array([r[1] for r in rows])
+    got = O.dist_a(A, O.KIND_LABELS_WEIGHTED, u, v, 0.0)
+    np.testing.assert_allclose(got, [r[2] for r in rows], rtol=0, atol=1e-12)
+    # symmetric; sharing a rarer label brings items closer than sharing a common one
+    assert np.array_equal(got, O.dist_a(A, O.KIND_LABELS_WEIGHTED, v, u, 0.0))
+    assert got[0] < got[2]
+    # capping as for the other kinds
+    capped = O.dist_a(A, O.KIND_LABELS_WEIGHTED, u, v, 1.0)
+    np.testing.assert_allclose(capped, np.maximum(got - 1.0, 0.0), atol=1e-12)
