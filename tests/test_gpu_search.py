@@ -88,6 +88,30 @@ def test_all_filter_types_match_oracle(mixed_world, L):
     assert n_ex >= 0.8 * w.nq
 
 
+@pytest.mark.parametrize("store", [jag.STORE_F32, jag.STORE_BF16])
+def test_wide_label_rows_match_oracle(store):
+    """Items with up to 10 Zipf labels of 1,000 (16-wide label rows inlined in
+    the adjacency rows), subset and Boolean queries, a graph from the host
+    builder with the weighted label distance; d = 128 spans several chunks."""
+    w = make_config("c3", n=5000, nq=120)
+    A = O.attrs_of(w)
+    _say("wide label rows, store", store)
+    adj, entry = jag.jag_build_graph(w.X, label_off=w.loff, labels=w.lab, vocab=w.vocab, R=32,
+                                     thresholds=[(jag.ATTR_LABELS_WEIGHTED, 1.0),
+                                                 (jag.ATTR_LABELS_WEIGHTED, 0.01),
+                                                 (jag.ATTR_LABELS_WEIGHTED, 0.0)], seed=3)
+    idx = _index(w, adj, entry, store=store, keep_f32=store != jag.STORE_F32)
+    assert idx.info().label_width == 16
+    Xs = w.X if store == jag.STORE_F32 else O.bf16_decode(O.bf16_encode(w.X))
+    for L in (16, 96):
+        g = gpu_search(idx, w.Q, w.F, w.pool, 10, L)
+        orc = O.search(Xs, adj, entry, A, w.Q, w.F, w.pool, L, 10)
+        n_ex, n_fl, n_fd = compare(g["ids"], g["d2"], g["count"], orc, tau_for(store, w.d),
+                                   _valid_fn(w, w.F, w.pool), f"wide labels L={L}")
+        _say(f"L={L}: exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
+        assert n_ex >= 0.8 * w.nq
+
+
 def test_quantizer_codes_bit_exact():
     """The device BF16 and FP8 stores hold exactly the oracle encoders' codes."""
     rng = np.random.default_rng(8)
