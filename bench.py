@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--op-mode", default="fp32-fixed",
                     choices=["fp32-fixed", "bf16+rerank-fixed", "learned+bf16+rerank"])
     ap.add_argument("--delta", type=float, default=0.0)
+    ap.add_argument("--ladder", default=None,
+                    help="profile mode, learned: comma-separated ladder (as the bench line reports it)")
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson arrivals)")
     ap.add_argument("--rates", default="5000,20000,50000,100000,200000")
@@ -92,6 +94,24 @@ class Timer:
 
 
 FILTER_NAMES = {0: "label", 1: "range", 2: "subset", 3: "boolean"}
+
+# beams of the fixed-beam sweeps (the kernel takes up to 1024)
+LADDER_FIXED = [10, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 56, 64, 80, 96, 128, 192, 256, 384, 512,
+                768, 1024]
+
+
+def learned_ladder(L95):
+    """Beams the predictor chooses from, sized to the workload: up to the
+    smallest sweep beam >= 1.4x the fixed beam that reaches recall 0.95 (at
+    least 64, all of them if none does), at most 16 entries spaced evenly in
+    log scale.  On the range workload this gives a ladder topping at 64,
+    which measured better than one to 128."""
+    top = 1024 if L95 is None else next((L for L in LADDER_FIXED if L >= max(64, 1.4 * L95)), 1024)
+    cand = [L for L in LADDER_FIXED if L <= top]
+    if len(cand) > 16:
+        want = np.exp(np.linspace(np.log(cand[0]), np.log(top), 16))
+        cand = sorted({min(cand, key=lambda L: abs(np.log(L) - np.log(x))) for x in want})
+    return np.array(cand, dtype=np.int32)
 
 # (attribute kind, quantile) lists: 0 scalar, 1 labels |a XOR b|, 2 labels with
 # the frequency-weighted distance the paper uses for skewed label vocabularies
@@ -149,8 +169,6 @@ def serve_main(args):
     kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
     ix = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_FP8_E4M3, keep_f32=True, **kw)
     Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
-    _, rho, rep = pred.fit(ix, Qt, Ft, pt, k=k, rerank_mult=4)
-    log(f"predictor: loss {rep.loss_first:.2f} -> {rep.loss_last:.2f}, rho {rho:.2f}")
     nthr = min(os.cpu_count() or 1, 16)
     A = O.attrs_of(w)
     gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, k, nthreads=nthr)
@@ -163,13 +181,25 @@ def serve_main(args):
                 r.append(len(set(gi[q, :den].tolist()) & set(ids_np[q].tolist())) / den)
         return float(np.mean(r))
 
-    # the smallest offset reaching recall 0.95 on the batch path
+    # the fixed beam that reaches recall 0.95 sizes the predictor's ladder
     dev = torch.device("cuda:0")
     rec = torch.from_numpy(jag.jag_encode_filters(ix, w.F, w.pool)).to(dev)
     Qd = torch.from_numpy(w.Q).to(dev)
     ids = torch.empty((w.nq, k), dtype=torch.int32, device=dev)
     dd = torch.empty((w.nq, k), dtype=torch.float32, device=dev)
     cnt = torch.empty((w.nq,), dtype=torch.int32, device=dev)
+    L95 = None
+    for L in LADDER_FIXED:
+        jag.jag_search_encoded(ix, Qd, rec, k, jag.SearchParams(L=L, rerank_mult=4), ids, dd, cnt)
+        torch.cuda.synchronize()
+        if recall_of(ids.cpu().numpy()) >= 0.95:
+            L95 = L
+            break
+    lad = learned_ladder(L95)
+    log(f"fixed beam at recall 0.95: {L95}; learned ladder {lad.tolist()}")
+    _, rho, rep = pred.fit(ix, Qt, Ft, pt, k=k, rerank_mult=4, ladder=lad)
+    log(f"predictor: loss {rep.loss_first:.2f} -> {rep.loss_last:.2f}, rho {rho:.2f}")
+    # the smallest offset reaching recall 0.95 on the batch path
     delta = None
     for dl in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]:
         sp = jag.SearchParams(L=k, learned=1, delta=dl, rerank_mult=4)
@@ -280,7 +310,9 @@ def main():
             ix, rec, sp = ix16, rec16, jag.SearchParams(L=args.L, rerank_mult=4)
         else:
             Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
-            pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4)
+            lad = (np.array([int(x) for x in args.ladder.split(",")], dtype=np.int32) if args.ladder
+                   else learned_ladder(None))
+            pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4, ladder=lad)
             ix, rec, sp = ix16, rec16, jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4)
         for i in range(args.warmup + args.steps):
             jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, d2, cnt)
@@ -328,7 +360,7 @@ def main():
                     nattr=float(st[:, 2].mean()), lhat=float(st[:, 3].mean()))
 
     # ---- plain FP32, fixed beam sweep
-    ladder_fixed = [10, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 56, 64, 80, 96, 128, 192, 256]
+    ladder_fixed = LADDER_FIXED
     fixed = []
     for L in ladder_fixed:
         r = point(ix32, rec32, jag.SearchParams(L=L))
@@ -350,11 +382,14 @@ def main():
     # ---- learned + BF16 + FP32 rerank
     learned = []
     fit_rep = None
+    lad = None
     if not args.only_fixed:
         t3 = time.time()
         Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
+        lad = learned_ladder(next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None))
+        log(f"learned ladder {lad.tolist()}")
         P, rho, fit_rep = pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4,
-                                   dump=args.dump_traces)
+                                   dump=args.dump_traces, ladder=lad)
         log(f"predictor fitted on {fit_rep.n_train} traces in {time.time() - t3:.1f}s: loss "
             f"{fit_rep.loss_first:.3f} -> {fit_rep.loss_last:.3f}, rho={rho:.2f}, "
             f"unreachable={fit_rep.unreachable}")
@@ -459,6 +494,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
         "operating_point": op_name,
+        "learned_ladder": None if lad is None else lad.tolist(),
         "cpu_baseline": cpu,
         "qps_at_095": {
             "learned_bf16_measured": best_l and round(best_l["qps"], 1),

@@ -129,10 +129,12 @@ typedef struct {
     int32_t learned;     /* 0 = fixed beam L; 1 = predicted beam (index needs a predictor);
                             2 = fixed beam L plus predictor features written to `features`.
                             In modes 1 and 2 the first four expansions keep a list of
-                            max(128, widest beam) entries (mode 1: the ladder's last
+                            max(64, widest beam) entries (mode 1: the ladder's last
                             entry, mode 2: L); the features are taken after the fourth
                             expansion and the list is then cut to the beam, which gives
-                            exactly the fixed-beam search's state */
+                            exactly the fixed-beam search's state.  Features from
+                            traces at L <= 64 match those of a learned search whose
+                            ladder tops out at 64 or less. */
     float delta;         /* learned mode: offset added to the predicted ladder index */
     int32_t rerank_mult; /* 0 = none; m > 0 rescores the best m*k entries of the final list
                             from the FP32 copy (needs keep_f32 or an FP32 store); m*k <= 64 */
@@ -153,8 +155,8 @@ typedef struct {
                             identical.  Two passes allocate stream-ordered device
                             scratch (hipMallocAsync on the call's stream) for each
                             query's saved state: (8 + 3*W + S + 1) * 4 bytes, W = list
-                            width (128 or the widest beam, rounded up to 64), S =
-                            seen-table slots (5.7 KB at W = 128, S = 1024); batches
+                            width (64 or the widest beam, rounded up to 64), S =
+                            seen-table slots (4.9 KB at W = 64, S = 1024); batches
                             needing more than 512 MiB run in chunks. */
 } jag_search_params;
 

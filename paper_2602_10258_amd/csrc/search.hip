@@ -977,8 +977,9 @@ ExactFn exact_for_ch(int ch)
 // 2^11 at fixed L = 44 and 64 (6-9 % more repeated evaluations, 14 % more
 // resident queries), 17-20 % faster for learned beams (128-entry list).
 constexpr int kDefaultHash = 1024;
-// List width of the first four expansions in learned and trace modes.
-constexpr int kWarmWidth = 128;
+// Smallest list width of the first four expansions in learned and trace
+// modes (the widest ladder beam, or L in trace mode, if larger).
+constexpr int kWarmWidth = 64;
 // Device memory a two-pass learned search may hold for saved states; larger
 // batches are processed in chunks of queries that fit.
 constexpr int64_t kStateBudget = int64_t(512) << 20;

@@ -152,13 +152,13 @@ def test_two_pass_schedule_is_exact(c1_small, mixed_world):
 
 
 def test_trace_features_are_beam_independent(c1_small):
-    """Trace mode writes the same features whatever the final beam (the first four
-    expansions keep every discovered vertex), and its answers equal fixed search."""
+    """Trace mode writes the same features for every beam up to 64 (the first four
+    expansions keep a 64-entry list), and its answers equal fixed search."""
     w, A, adj, entry = c1_small
     idx = jag.jag_build_from_graph(w.X, adj, entry, label_off=w.loff, labels=w.lab, vocab=8)
     a = gpu_search(idx, w.Q, w.F, w.pool, 10, 16, learned=2, features=True)
-    b = gpu_search(idx, w.Q, w.F, w.pool, 10, 96, learned=2, features=True)
-    f = gpu_search(idx, w.Q, w.F, w.pool, 10, 96)
+    b = gpu_search(idx, w.Q, w.F, w.pool, 10, 64, learned=2, features=True)
+    f = gpu_search(idx, w.Q, w.F, w.pool, 10, 64)
     assert np.array_equal(a["features"], b["features"])
     assert np.all(a["features"][:, 15] == 1.0)
     onehot = a["features"][:, :4]
