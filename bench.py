@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--rates", default="5000,20000,50000,100000,200000")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="profile mode: also run device copies of this many bytes")
+    ap.add_argument("--min-valid", type=int, default=None,
+                    help="drop queries with fewer valid items (default: k for the label-set "
+                         "workloads c3 and c5, else 0)")
     ap.add_argument("--filter-type", type=int, default=None, choices=[0, 1, 2, 3],
                     help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--graph-cache", default=None,
@@ -172,6 +175,10 @@ def serve_main(args):
     nthr = min(os.cpu_count() or 1, 16)
     A = O.attrs_of(w)
     gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, k, nthreads=nthr)
+    keep = nv >= (args.min_valid if args.min_valid is not None else k)
+    log(f"keeping {int(keep.sum())} of {len(keep)} queries with >= k valid items")
+    w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
+    gi, gd, nv = gi[keep], gd[keep], nv[keep]
 
     def recall_of(ids_np):
         r = []
@@ -335,6 +342,21 @@ def main():
     A = O.attrs_of(w)
     gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, k, nthreads=nthr)
     log(f"exact answers (oracle, {nthr} threads) in {time.time() - t2:.1f}s")
+    min_valid = args.min_valid if args.min_valid is not None else (k if w.name in ("c3", "c5") else 0)
+    if min_valid > 0 and (nv < min_valid).any():
+        # label-set workloads keep only queries with at least k valid items
+        keep = nv >= min_valid
+        log(f"keeping {int(keep.sum())} of {len(keep)} queries with >= {min_valid} valid items")
+        w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
+        gi, gd, nv = gi[keep], gd[keep], nv[keep]
+        rec32 = torch.from_numpy(jag.jag_encode_filters(ix32, w.F, w.pool)).to(dev)
+        rec16 = torch.from_numpy(jag.jag_encode_filters(ix16, w.F, w.pool)).to(dev)
+        Qd = torch.from_numpy(w.Q).to(dev)
+        nq = w.nq
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        d2 = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        cnt = torch.empty((nq,), dtype=torch.int32, device=dev)
+        stats = torch.zeros((nq, 4), dtype=torch.int32, device=dev)
     has_valid = nv > 0
 
     def recall(ids_np):

@@ -944,15 +944,19 @@ SearchFn pick_search_wpe(int store, int G, int ch)
     return G == 4 ? search_for_ch<JAG_STORE_FP8_E4M3, 4, WPE>(ch) : search_for_ch<JAG_STORE_FP8_E4M3, 16, WPE>(ch);
 }
 
-// Fixed-beam searches use the build for 5 waves per SIMD (at most 96 VGPRs,
-// a few spills to scratch outside the hop loop): 8-12 % faster than 4 waves
-// on the range workload.  Learned and trace modes (128-entry warm-up list,
-// two launches) measured faster with the 4-wave build (no scratch).
-SearchFn pick_search(int store, int stride, int mode)
+// All modes use the build for 5 waves per SIMD (at most 96 VGPRs; the
+// allocator spills 20-60 bytes per lane to scratch): on the range workload
+// 8-12 % faster than the 4-wave build (100-128 VGPRs, no scratch) for fixed
+// beams, and 7-10 % faster for two-pass learned search with a 64-entry
+// warm-up list.  (With a 128-entry warm-up the 4-wave build had been faster
+// for learned search.)
+constexpr int kWavesPerSimd = 5;
+
+SearchFn pick_search(int store, int stride, int /*mode*/)
 {
     int G = pick_group(stride);
     int ch = stride / (16 * G);
-    return mode == 0 ? pick_search_wpe<5>(store, G, ch) : pick_search_wpe<4>(store, G, ch);
+    return pick_search_wpe<kWavesPerSimd>(store, G, ch);
 }
 
 template <int G>
