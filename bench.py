@@ -372,7 +372,7 @@ def main():
     def point(ix, rec, sp):
         def fn():
             jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, d2, cnt)
-        ms = timer.run(fn, reps=3, warm=1)
+        ms = timer.run(fn, reps=7, warm=1)
         sp2 = jag.SearchParams(**{**sp.__dict__, "stats": stats})
         jag.jag_search_encoded(ix, Qd, rec, k, sp2, ids, d2, cnt)
         torch.cuda.synchronize()

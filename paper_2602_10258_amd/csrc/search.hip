@@ -1281,7 +1281,17 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     }
     // two passes over chunks of queries: run each to its prediction and save
     // its state (list, seen-table, counters), order the chunk by predicted
-    // beam, widest first, then resume every search in that order
+    // beam, widest first, then resume every search in that order.  The
+    // scratch comes from the device's default memory pool, which is told to
+    // keep freed memory reserved so that repeated searches do not go back to
+    // the driver for it.
+    {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, ix.device) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     const int64_t stride = state_words(a.Lcap, a.Hmask + 1);
     const int64_t per_q = (stride + 1) * (int64_t)sizeof(int32_t);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
