@@ -475,6 +475,18 @@ def main():
     value = nq / (ms_per_step / 1e3)
     rec_final = recall(ids.cpu().numpy())
 
+    # end to end from host filters: encoding, record upload and search
+    # (jag_search_batch), query vectors and outputs already on the device
+    def step_host():
+        jag.jag_search_batch(op["ix"], Qd, w.F, w.pool, k, op["sp"], ids, d2, cnt)
+    step_host()
+    torch.cuda.synchronize()
+    t_h = time.perf_counter()
+    for _ in range(args.steps):
+        step_host()
+    torch.cuda.synchronize()
+    e2e_qps = nq * args.steps / (time.perf_counter() - t_h)
+
     # ---- roofline: algorithmic bytes of one launch / its average duration
     sp2 = jag.SearchParams(**{**op["sp"].__dict__, "stats": stats})
     jag.jag_search_encoded(op["ix"], Qd, op["rec"], k, sp2, ids, d2, cnt)
@@ -529,6 +541,7 @@ def main():
             "bf16_rerank_fixed_L": best_f16 and best_f16["L"],
         },
         "kernel_ms": round(kern_ms, 4),
+        "host_filters_qps": round(e2e_qps, 1),
         "alg_bytes_per_query": round(alg_bytes / nq, 1),
         "mean_expansions": round(float(st[:, 0].mean()), 2),
         "mean_distance_computations": round(float(st[:, 1].mean()), 2),
