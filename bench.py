@@ -165,7 +165,7 @@ def serve_main(args):
     else:
         adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
                                          vocab=w.vocab, R=w.R, L_build=2 * w.R,
-                                         thresholds=THRESHOLDS["c5"], seed=0)
+                                         thresholds=THRESHOLDS["c5"], seed=0, progress=True)
         if args.graph_cache:
             np.savez(args.graph_cache, adj=adj, entry=entry)
     log(f"graph ready in {time.time() - t1:.1f}s")
@@ -292,7 +292,7 @@ def main():
     else:
         adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
                                          vocab=w.vocab, R=w.R, L_build=2 * w.R,
-                                         thresholds=THRESHOLDS[w.name], seed=0)
+                                         thresholds=THRESHOLDS[w.name], seed=0, progress=True)
         if args.graph_cache:
             np.savez(args.graph_cache, adj=adj, entry=entry)
     build_s = time.time() - t1

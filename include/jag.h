@@ -101,6 +101,7 @@ typedef struct {
     uint64_t seed;            /* insertion order and threshold sampling */
     int32_t n_threads;        /* host builder threads; 0 = all hardware threads */
     int32_t max_batch;        /* cap on points inserted per parallel round; 0 = max(64, n/50) */
+    int32_t progress;         /* 1 = print one line to stderr per tenth of the points inserted */
 } jag_build_params;
 
 /*

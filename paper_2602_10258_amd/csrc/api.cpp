@@ -333,6 +333,7 @@ static jag_status make_config(const float *X, int64_t n, int32_t d, const jag_at
     cfg.seed = P->seed;
     cfg.n_threads = P->n_threads;
     cfg.max_batch = P->max_batch;
+    cfg.progress = P->progress;
     for (int i = 0; i < P->n_thr; i++) {
         int kind = P->thr[i].kind;
         if (kind == JAG_ATTR_SCALAR && !(A && A->scalar)) {

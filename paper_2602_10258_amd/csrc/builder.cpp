@@ -10,6 +10,7 @@
 // Every write touches one vertex's row from one task, so the graph depends
 // only on the seed, not on thread count or timing.
 #include <algorithm>
+#include <cstdio>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -426,6 +427,10 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
                 B.deg[v] = m;
             }
         }, 16);
+        if (cfg.progress && (pos * 10) / n != (be * 10) / n) {
+            std::fprintf(stderr, "[build] %lld of %lld points inserted\n", (long long)be, (long long)n);
+            std::fflush(stderr);
+        }
         pos = be;
         bs = std::min<int64_t>(bs * 2, max_batch);
     }

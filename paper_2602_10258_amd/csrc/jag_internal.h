@@ -94,6 +94,7 @@ struct BuildConfig {
     uint64_t seed = 0;
     int32_t n_threads = 0;
     int32_t max_batch = 0;
+    int32_t progress = 0;
 };
 
 struct AttrView {

@@ -45,7 +45,7 @@ class jag_build_params(C.Structure):
     _fields_ = [("R", C.c_int32), ("L_build", C.c_int32), ("alpha", C.c_float),
                 ("n_thr", C.c_int32), ("thr", C.POINTER(jag_threshold)), ("store", C.c_int32),
                 ("keep_f32", C.c_int32), ("seed", C.c_uint64), ("n_threads", C.c_int32),
-                ("max_batch", C.c_int32)]
+                ("max_batch", C.c_int32), ("progress", C.c_int32)]
 
 
 class jag_search_params(C.Structure):
@@ -142,11 +142,11 @@ def _attrs(scalar, label_off, labels, vocab):
     return a, keep
 
 
-def _params(R, L_build, alpha, thresholds, store, keep_f32, seed, n_threads, max_batch):
+def _params(R, L_build, alpha, thresholds, store, keep_f32, seed, n_threads, max_batch, progress=False):
     thr = (jag_threshold * max(1, len(thresholds)))(*[jag_threshold(int(k), float(q)) for k, q in thresholds])
     p = jag_build_params(int(R), int(L_build), float(alpha), len(thresholds),
                          C.cast(thr, C.POINTER(jag_threshold)), int(store), int(keep_f32),
-                         int(seed), int(n_threads), int(max_batch))
+                         int(seed), int(n_threads), int(max_batch), int(bool(progress)))
     return p, thr
 
 
@@ -192,11 +192,11 @@ def jag_build(X, scalar=None, label_off=None, labels=None, vocab=0, R=32, L_buil
 
 def jag_build_graph(X, scalar=None, label_off=None, labels=None, vocab=0, R=32, L_build=0,
                     alpha=1.2, thresholds: Sequence = ((ATTR_SCALAR, 1.0),), seed=0, n_threads=0,
-                    max_batch=0):
+                    max_batch=0, progress=False):
     """Host-only Threshold-JAG construction; returns (adj int32[n, R], entry)."""
     X = _np(X, np.float32)
     a, keep = _attrs(scalar, label_off, labels, vocab)
-    p, thr = _params(R, L_build, alpha, thresholds, STORE_F32, 0, seed, n_threads, max_batch)
+    p, thr = _params(R, L_build, alpha, thresholds, STORE_F32, 0, seed, n_threads, max_batch, progress)
     adj = np.empty((X.shape[0], R), dtype=np.int32)
     e = C.c_int32()
     _check(lib().jag_build_graph(_ptr(X), X.shape[0], X.shape[1], C.byref(a), C.byref(p), _ptr(adj),
