@@ -54,7 +54,7 @@ def parse():
                     help="run only the operating point (for rocprofv3); needs --L and --store")
     ap.add_argument("--L", type=int, default=48)
     ap.add_argument("--op-mode", default="fp32-fixed",
-                    choices=["fp32-fixed", "bf16+rerank-fixed", "learned+bf16+rerank"])
+                    choices=["fp32-fixed", "bf16+rerank-fixed", "fp8+rerank-fixed", "learned+bf16+rerank"])
     ap.add_argument("--delta", type=float, default=0.0)
     ap.add_argument("--ladder", default=None,
                     help="profile mode, learned: comma-separated ladder (as the bench line reports it)")
@@ -315,6 +315,10 @@ def main():
             ix, rec, sp = ix32, rec32, jag.SearchParams(L=args.L)
         elif args.op_mode == "bf16+rerank-fixed":
             ix, rec, sp = ix16, rec16, jag.SearchParams(L=args.L, rerank_mult=4)
+        elif args.op_mode == "fp8+rerank-fixed":
+            ix = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_FP8_E4M3, keep_f32=True, **kw)
+            rec = torch.from_numpy(jag.jag_encode_filters(ix, w.F, w.pool)).to(dev)
+            sp = jag.SearchParams(L=args.L, rerank_mult=4)
         else:
             Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
             lad = (np.array([int(x) for x in args.ladder.split(",")], dtype=np.int32) if args.ladder
@@ -400,6 +404,17 @@ def main():
         log(f"bf16+rerank L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
         if r["recall"] >= 0.99:
             break
+    # ---- ablation: FP8 E4M3 (per-row scale) + FP32 rerank, beams around BF16's 0.95 point
+    fixed8 = []
+    L95 = next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None)
+    if L95 is not None and not args.only_fixed:
+        ix8 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_FP8_E4M3, keep_f32=True, **kw)
+        rec8 = torch.from_numpy(jag.jag_encode_filters(ix8, w.F, w.pool)).to(dev)
+        for L in [L for L in ladder_fixed if L95 / 2 <= L <= 2 * L95]:
+            r = point(ix8, rec8, jag.SearchParams(L=L, rerank_mult=4))
+            r["L"] = L
+            fixed8.append(r)
+            log(f"fp8+rerank L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
 
     # ---- learned + BF16 + FP32 rerank
     learned = []
@@ -437,6 +452,7 @@ def main():
 
     best_f, interp_f = at95(fixed)
     best_f16, interp_f16 = at95(fixed16)
+    best_f8, interp_f8 = at95(fixed8) if fixed8 else (None, None)
     best_l, interp_l = at95(learned) if learned else (None, None)
     cands = []
     if best_l:
@@ -450,6 +466,10 @@ def main():
     if best_f:
         cands.append(dict(mode="fp32-fixed", ix=ix32, rec=rec32, sp=jag.SearchParams(L=best_f["L"]),
                           store=jag.STORE_F32, rerank=False, point=best_f))
+    if best_f8:
+        cands.append(dict(mode="fp8+rerank-fixed", ix=ix8, rec=rec8,
+                          sp=jag.SearchParams(L=best_f8["L"], rerank_mult=4),
+                          store=jag.STORE_FP8_E4M3, rerank=True, point=best_f8))
     assert cands, "no configuration reached recall 0.95"
     op = max(cands, key=lambda c: c["point"]["qps"])
     log(f"operating point: {op['mode']} ({op['point']})")
@@ -524,7 +544,8 @@ def main():
                                f"({w.meta.get('thresholds')}), k={k}, R={w.R}",
                    "global_batch": nq, "mode": op["mode"], "recall_at_10": round(rec_final, 4),
                    "filter_types": sorted({FILTER_NAMES[int(t)] for t in w.F[:, 0]}),
-                   "storage": "bf16 (+fp32 rerank)" if op["rerank"] else "fp32"},
+                   "storage": {jag.STORE_F32: "fp32", jag.STORE_BF16: "bf16 (+fp32 rerank)",
+                               jag.STORE_FP8_E4M3: "fp8 e4m3 + row scale (+fp32 rerank)"}[op["store"]]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
         "operating_point": op_name,
@@ -539,6 +560,9 @@ def main():
             "bf16_rerank_fixed_measured": best_f16 and round(best_f16["qps"], 1),
             "bf16_rerank_fixed_interp": interp_f16 and round(interp_f16, 1),
             "bf16_rerank_fixed_L": best_f16 and best_f16["L"],
+            "fp8_rerank_fixed_measured": best_f8 and round(best_f8["qps"], 1),
+            "fp8_rerank_fixed_interp": interp_f8 and round(interp_f8, 1),
+            "fp8_rerank_fixed_L": best_f8 and best_f8["L"],
         },
         "kernel_ms": round(kern_ms, 4),
         "host_filters_qps": round(e2e_qps, 1),
@@ -550,6 +574,8 @@ def main():
                              for r in fixed],
                    "bf16_rerank_fixed": [{k_: (round(v, 4) if isinstance(v, float) else v)
                                           for k_, v in r.items()} for r in fixed16],
+                   "fp8_rerank_fixed": [{k_: (round(v, 4) if isinstance(v, float) else v)
+                                         for k_, v in r.items()} for r in fixed8],
                    "learned": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
                                for r in learned]},
         "predictor": fit_rep and fit_rep.__dict__,
