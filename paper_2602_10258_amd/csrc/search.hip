@@ -371,6 +371,62 @@ __device__ __forceinline__ int first_unexpanded(const Lds &s, int from, int cnt)
     return cnt;
 }
 
+// Merge for a list of at most 64 entries and at most kSmallMerge survivors:
+// lane j holds list entry j in registers; the survivors are visited one by
+// one (their key broadcast with readlane), and one ballot over the list gives
+// each survivor's insertion point and another tells whether it is already in
+// the list.  In the same pass list lanes count the survivors ahead of them
+// and candidate lanes their rank among the survivors; then every entry is
+// written once to its final slot.  No LDS round trips inside the pass.
+// Larger survivor sets take the binary-search merge below.  On the range
+// workload (BF16, L = 44) thresholds 8 / 16 / 32 measured 0.727 / 0.734 /
+// 0.764 ms per launch against 0.751 ms with the binary-search merge alone.
+constexpr int kSmallMerge = 8;
+
+__device__ __forceinline__ int merge_small(const Lds &s, int cnt, int ls, bool have, uint64_t ck, uint32_t ci,
+                                           uint64_t vm, int *minpos)
+{
+    const int lane = threadIdx.x;
+    const bool inl = lane < cnt;
+    const uint64_t lk = inl ? s.key[lane] : 0ull;
+    const uint32_t lidf = inl ? s.idf[lane] : 0u;
+    const uint32_t li = lidf & kIdMask;
+    int sh = 0, rank = 0, mypos = 0, nkeep = 0, mp = ls;
+    bool dup = false;
+    for (uint64_t mm = vm; mm; mm &= mm - 1) {
+        const int d = __builtin_ctzll(mm);
+        const uint32_t dkh = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(ck >> 32), d);
+        const uint32_t dkl = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ck, d);
+        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)ci, d);
+        const uint64_t dk = ((uint64_t)dkh << 32) | dkl;
+        const int pd = __popcll(ballot64(inl && key_lt(lk, li, dk, di)));
+        const bool isdup = ballot64(inl && lk == dk && li == di) != 0;
+        if (lane == d) {
+            mypos = pd;
+            dup = isdup;
+        }
+        if (!isdup) {
+            nkeep++;
+            sh += (inl && pd <= lane) ? 1 : 0;
+            rank += (have && key_lt(dk, di, ck, ci)) ? 1 : 0;
+            mp = pd < mp ? pd : mp;
+        }
+    }
+    __syncthreads();
+    if (inl && lane + sh < ls) {
+        s.key[lane + sh] = lk;
+        s.idf[lane + sh] = lidf;
+    }
+    if (have && !dup && mypos + rank < ls) {
+        s.key[mypos + rank] = ck;
+        s.idf[mypos + rank] = ci;
+    }
+    __syncthreads();
+    *minpos = nkeep ? mp : ls;
+    const int nc = cnt + nkeep;
+    return nc < ls ? nc : ls;
+}
+
 // Merge candidates (lane c < m holds cid/cdf/cd2 slot c) into the sorted
 // list of cnt entries, keeping at most ls.  Returns the new size; *minpos is
 // the list position of the best inserted candidate (ls if none).
@@ -388,6 +444,14 @@ __device__ int merge_candidates(const Lds &s, int m, int cnt, int ls, int *minpo
         uint64_t wk = s.key[cnt - 1];
         uint32_t wi = s.idf[cnt - 1] & kIdMask;
         if (!key_lt(ck, ci, wk, wi)) have = false;
+    }
+    {
+        const uint64_t vm0 = ballot64(have);
+        if (vm0 == 0) {
+            *minpos = ls;
+            return cnt;
+        }
+        if (cnt <= 64 && __popcll(vm0) <= kSmallMerge) return merge_small(s, cnt, ls, have, ck, ci, vm0, minpos);
     }
     int pos = 0;
     if (have) {
