@@ -155,7 +155,7 @@ typedef struct {
                             beams; 1 = one launch in submission order.  Results are
                             identical.  Two passes allocate stream-ordered device
                             scratch (hipMallocAsync on the call's stream) for each
-                            query's saved state: (8 + 3*W + S + 1) * 4 bytes, W = list
+                            query's saved state: (8 + 3*W + S + 2) * 4 bytes, W = list
                             width (64 or the widest beam, rounded up to 64), S =
                             seen-table slots (4.9 KB at W = 64, S = 1024); batches
                             needing more than 512 MiB run in chunks. */

@@ -55,6 +55,7 @@ struct SearchArgs {
     int32_t L, Lcap, Hmask, k, rerank, max_hops, mode, nladder, warm;
     const int32_t *perm;  // query handled by each workgroup (null: identity)
     int32_t *state;       // modes 3 and 4: saved search state, state_stride words per query
+    int32_t *order_key;   // mode 3: 1 + predicted ladder index per query (0: ended before)
     int64_t state_stride;
     float delta, rho;
     int32_t ladder[JAG_LADDER_MAX];
@@ -719,6 +720,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                               : lane == 4 ? ndist : lane == 5 ? nattr : lane == 6 ? hopcap : lhat;
                         ws[lane] = v;
                     }
+                    if (lane == 0) a.order_key[q] = idx + 1;
                     return;
                 }
             }
@@ -727,7 +729,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     if (a.mode == 2 && !predicted && lane < 16)  // fewer than four expansions: no features
         a.features[q * 16 + lane] = lane == 15 ? -1.f : 0.f;
     if (a.mode == 3) {  // ended before the prediction point: the search pass redoes it
-        if (lane == 0) a.state[q * a.state_stride] = 0;
+        if (lane == 0) {
+            a.state[q * a.state_stride] = 0;
+            a.order_key[q] = 0;
+        }
         return;
     }
     // ---- output: top-k valid entries, optionally rescored in FP32
@@ -904,15 +909,14 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
 
 // ---------------------------------------------------------------- schedule
 // Longest-predicted-first order for the search pass of a two-pass learned
-// search: a stable counting sort of the queries by the first word of their
-// saved state, 1 + predicted ladder index (0 = finished before the
-// prediction point), largest first.  One workgroup; thread t owns the
-// contiguous chunk [t*chunk, (t+1)*chunk) of queries.
+// search: a stable counting sort of the queries by key = 1 + predicted
+// ladder index (0 = finished before the prediction point), largest first.
+// One workgroup; thread t owns the contiguous chunk [t*chunk, (t+1)*chunk)
+// of queries.
 constexpr int kOrderThreads = 512;
 constexpr int kOrderBins = JAG_LADDER_MAX + 1;
 
-__global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *state, int64_t stride, int64_t nq,
-                                                               int32_t *perm)
+__global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key, int64_t nq, int32_t *perm)
 {
     __shared__ int32_t cnt[kOrderBins][kOrderThreads];
     __shared__ int32_t part[kOrderThreads];
@@ -922,7 +926,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *sta
     const int64_t b1 = b0 + chunk < nq ? b0 + chunk : nq;
     for (int b = 0; b < kOrderBins; b++) cnt[b][t] = 0;
     for (int64_t i = b0; i < b1; i++) {
-        int k = state[i * stride];
+        int k = key[i];
         k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
         cnt[k][t]++;
     }
@@ -953,7 +957,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *sta
     }
     __syncthreads();
     for (int64_t i = b0; i < b1; i++) {
-        int k = state[i * stride];
+        int k = key[i];
         k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
         perm[cnt[k][t]++] = (int32_t)i;
     }
@@ -1254,6 +1258,7 @@ static jag_status fill_args(Index &ix, SearchArgs &a, const float *Q, const void
     a.perm = nullptr;
     a.state = nullptr;
     a.state_stride = 0;
+    a.order_key = nullptr;
     return JAG_OK;
 }
 
@@ -1357,11 +1362,12 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         }
     }
     const int64_t stride = state_words(a.Lcap, a.Hmask + 1);
-    const int64_t per_q = (stride + 1) * (int64_t)sizeof(int32_t);
+    const int64_t per_q = (stride + 2) * (int64_t)sizeof(int32_t);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
     int32_t *scratch = nullptr;
     HIPCHK(hipMallocAsync((void **)&scratch, (size_t)(chunk * per_q), sm));
     int32_t *perm = scratch + chunk * stride;
+    int32_t *okey = perm + chunk;
     hipError_t e = hipSuccess;
     for (int64_t c0 = 0; c0 < nq && e == hipSuccess; c0 += chunk) {
         const int64_t nc = std::min(chunk, nq - c0);
@@ -1374,13 +1380,14 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         b.stats = a.stats ? a.stats + c0 * 4 : nullptr;
         b.state = scratch;
         b.state_stride = stride;
+        b.order_key = okey;
         SearchArgs b3 = b;
         b3.mode = 3;
         b3.stats = nullptr;
         hipLaunchKernelGGL(fn, dim3((unsigned)nc), dim3(64), lds, sm, b3);
         e = hipGetLastError();
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, scratch, stride, nc, perm);
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, okey, nc, perm);
         e = hipGetLastError();
         if (e != hipSuccess) break;
         b.mode = 4;
@@ -1427,7 +1434,7 @@ jag_status search_scratch_bytes(Index &ix, int32_t k, const jag_search_params &S
     if (st != JAG_OK) return st;
     *bytes = 0;
     if (S.learned == 1 && !S.single_pass && nq >= 2) {
-        const int64_t per_q = (state_words(a.Lcap, a.Hmask + 1) + 1) * (int64_t)sizeof(int32_t);
+        const int64_t per_q = (state_words(a.Lcap, a.Hmask + 1) + 2) * (int64_t)sizeof(int32_t);
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
         *bytes = chunk * per_q;
     }
