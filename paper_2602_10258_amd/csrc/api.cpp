@@ -7,6 +7,9 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "jag_internal.h"
 
@@ -133,10 +136,11 @@ double label_freq(const Index &ix, int32_t l)
 
 }  // namespace
 
-jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
-                          int64_t pool_len, FilterRecord *out)
+// Encode queries [q0, q1); stops at the first bad filter (message via set_error).
+static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0, int64_t q1,
+                               const int32_t *pool, int64_t pool_len, FilterRecord *out)
 {
-    for (int64_t q = 0; q < nq; q++) {
+    for (int64_t q = q0; q < q1; q++) {
         const jag_filter &f = F[q];
         FilterRecord r;
         std::memset(&r, 0, sizeof(r));
@@ -292,6 +296,33 @@ jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, cons
         r.sel_feature = (float)(std::log2(std::max(sel, 1e-9)) / 16.0);
         out[q] = r;
     }
+    return JAG_OK;
+}
+
+jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                          int64_t pool_len, FilterRecord *out)
+{
+    // large batches are encoded by several host threads (the range
+    // selectivity estimate is two binary searches over the sorted scalars)
+    constexpr int64_t kPerThread = 2048;
+    const int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()),
+                                           std::min<int64_t>(16, nq / kPerThread));
+    if (nth <= 1) return encode_range(ix, F, 0, nq, pool, pool_len, out);
+    std::vector<jag_status> st(nth, JAG_OK);
+    std::vector<std::string> msg(nth);
+    std::vector<std::thread> th;
+    const int64_t chunk = (nq + nth - 1) / nth;
+    for (int t = 0; t < nth; t++)
+        th.emplace_back([&, t]() {
+            st[t] = encode_range(ix, F, t * chunk, std::min(nq, (t + 1) * chunk), pool, pool_len, out);
+            if (st[t] != JAG_OK) msg[t] = g_err;  // the worker's own thread-local message
+        });
+    for (auto &x : th) x.join();
+    for (int t = 0; t < nth; t++)
+        if (st[t] != JAG_OK) {  // the first bad query in batch order
+            set_error("%s", msg[t].c_str());
+            return st[t];
+        }
     return JAG_OK;
 }
 

@@ -185,6 +185,25 @@ def test_exact_knn_matches_bruteforce(c1_small):
     assert np.array_equal(cnt.cpu().numpy(), np.minimum(nv, k))
 
 
+def test_large_batch_encoding_matches_small_batches(mixed_world):
+    """Batches of 2,048+ filters are encoded by several host threads: the records
+    equal those of small (single-thread) batches byte for byte, and a bad filter
+    is reported by its own index, the first one in batch order."""
+    w, A, adj, entry = mixed_world
+    idx = _index(w, adj, entry)
+    reps = 80  # 12,800 filters of all four types
+    F = np.tile(w.F, (reps, 1))
+    big = jag.jag_encode_filters(idx, F, w.pool)
+    small = np.concatenate([jag.jag_encode_filters(idx, F[i:i + 1000], w.pool)
+                            for i in range(0, len(F), 1000)])
+    assert big.shape == small.shape and np.array_equal(big, small)
+    bad = F.copy()
+    bad[9001, 0] = 7        # unknown filter type
+    bad[11000, 0] = 9
+    with pytest.raises(jag.JagError, match="query 9001"):
+        jag.jag_encode_filters(idx, bad, w.pool)
+
+
 def test_edge_cases(mixed_world):
     import torch
     w, A, adj, entry = mixed_world
