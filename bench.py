@@ -262,7 +262,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md and not built.", file=sys.stderr)
+              "a layout over several GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         return serve_main(args)

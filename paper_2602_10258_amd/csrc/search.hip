@@ -1352,8 +1352,8 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     // its state (list, seen-table, counters), order the chunk by predicted
     // beam, widest first, then resume every search in that order.  The
     // scratch comes from the device's default memory pool, which is told to
-    // keep freed memory reserved so that repeated searches do not go back to
-    // the driver for it.
+    // keep freed memory reserved so that repeated searches do not return it
+    // to the system and allocate it again.
     {
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, ix.device) == hipSuccess) {
