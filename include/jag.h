@@ -63,7 +63,8 @@ typedef enum {
     JAG_LABEL = 0,   /* item's label set contains `label` (equality for one-label items) */
     JAG_RANGE = 1,   /* lo <= scalar attribute <= hi (inclusive) */
     JAG_SUBSET = 2,  /* item's label set contains every label of pool[off, off+len) */
-    JAG_BOOLEAN = 3  /* DNF program in pool[off, off+len): see jag_filter */
+    JAG_BOOLEAN = 3, /* DNF program in pool[off, off+len): see jag_filter */
+    JAG_TABLE = 4    /* general Boolean function given by its truth table: see jag_filter */
 } jag_filter_type;
 
 /* Attribute distances dist_A the threshold list can name, one per entry
@@ -114,6 +115,14 @@ typedef struct {
  *            1..8 clauses, at most 16 literals in all; a literal l >= 0 asks
  *            for label l, l < 0 asks for the absence of label ~l.  Repeated
  *            literals count once; a clause holding l and ~l never holds.
+ *   TABLE:   off, len -> an arbitrary Boolean function of nvar labels
+ *            (Section 2's general Boolean filter): pool holds
+ *              nvar, var_0, ..., var_{nvar-1}, w_0, ..., w_{W-1}
+ *            with 1 <= nvar <= 15 distinct labels and W = ceil(2^nvar / 32)
+ *            words; an item's assignment x has bit v set when it holds
+ *            label var_v, and the function is true on x when bit x % 32 of
+ *            word w_{x / 32} is set.  dist_F = the fewest label flips that
+ *            make it true (Section 3.1).  Encode with jag_encode_filters_sized.
  */
 typedef struct {
     int32_t type, label, lo, hi, off, len;
@@ -233,15 +242,33 @@ jag_status jag_get_store(const jag_index *idx, void *rows_out, float *scales_out
  * the device once and reused by jag_search_encoded.
  * Errors: EINVAL (unknown type, malformed pool program, label outside
  * [0, vocab), RANGE on an index without scalars, label filters on an index
- * without labels, too many labels/literals/clauses).
+ * without labels, too many labels/literals/clauses, TABLE filters: their
+ * distance tables need jag_encode_filters_sized).
  */
 jag_status jag_encode_filters(const jag_index *idx, const jag_filter *F, int64_t nq,
                               const int32_t *pool, int64_t pool_len, void *records_out);
 
+/* Size in bytes of the encoding of F by jag_encode_filters_sized: nq records
+ * followed by one distance table of 2^nvar bytes per TABLE filter (16-byte
+ * aligned).  Errors: EINVAL (malformed TABLE span). */
+jag_status jag_encoded_bytes(const jag_index *idx, const jag_filter *F, int64_t nq,
+                             const int32_t *pool, int64_t pool_len, int64_t *bytes);
+
+/* Like jag_encode_filters, for any filter type: out (host, out_bytes >=
+ * jag_encoded_bytes) receives the nq records, then the distance tables of
+ * the TABLE filters; each such record locates its table by a byte offset
+ * from itself, so the whole buffer is copied to the device as one block
+ * and passed to jag_search_encoded as `records`.  Errors: as
+ * jag_encode_filters, plus EINVAL when out_bytes is too small. */
+jag_status jag_encode_filters_sized(const jag_index *idx, const jag_filter *F, int64_t nq,
+                                    const int32_t *pool, int64_t pool_len, void *out,
+                                    int64_t out_bytes);
+
 /*
  * Filtered greedy search (Algorithm 2 over Algorithm 1) for nq queries,
  * one GPU wavefront per query.  Q: device float[nq][d].  records: device,
- * from jag_encode_filters.  Outputs (device): ids[nq][k] valid item ids
+ * from jag_encode_filters or jag_encode_filters_sized (the whole buffer).
+ * Outputs (device): ids[nq][k] valid item ids
  * (those with dist_F = 0) in increasing (dist, id) order, padded with -1;
  * dists[nq][k] the matching squared distances (from the FP32 copy when
  * reranking, else from the store; +inf for padding); count[nq] the number

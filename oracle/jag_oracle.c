@@ -35,6 +35,7 @@
 #define OR_F_RANGE 1
 #define OR_F_SUBSET 2
 #define OR_F_BOOLEAN 3
+#define OR_F_TABLE 4
 
 #define OR_KIND_SCALAR 0
 #define OR_KIND_LABELS 1
@@ -84,9 +85,45 @@ static int literal_true(const or_attrs *A, int64_t i, int32_t lit)
  *  so its cost is the number of its distinct literals that are false, and
  *  f costs the cheapest clause.  A clause holding a literal and its
  *  negation can never be satisfied and is skipped.
+ *  Table: a general Boolean function of nvar labels given by its truth
+ *  table; the item's assignment x has bit v set when it holds label var_v,
+ *  and the distance is the least Hamming distance from x to an assignment
+ *  on which the function is true (Section 3.1's definition, by brute force
+ *  over all 2^nvar assignments).
  */
+static double table_dist(const or_attrs *A, int64_t i, const or_filter *f, const int32_t *pool)
+{
+    const int32_t *p = pool + f->off;
+    int32_t nv = p[0];
+    const int32_t *vars = p + 1;
+    const uint32_t *w = (const uint32_t *)(p + 1 + nv);
+    uint32_t x = 0;
+    for (int32_t v = 0; v < nv; v++)
+        if (item_has(A, i, vars[v])) x |= 1u << v;
+    double best = OR_UNSAT;
+    for (uint32_t y = 0; y < (1u << nv); y++) {
+        if (!((w[y >> 5] >> (y & 31)) & 1u)) continue;
+        double h = (double)__builtin_popcount(x ^ y);
+        if (h < best) best = h;
+    }
+    return best;
+}
+
+/* g(a_i, f) of Section 2 for a table filter: the function's value on the item. */
+static int table_true(const or_attrs *A, int64_t i, const or_filter *f, const int32_t *pool)
+{
+    const int32_t *p = pool + f->off;
+    int32_t nv = p[0];
+    const uint32_t *w = (const uint32_t *)(p + 1 + nv);
+    uint32_t x = 0;
+    for (int32_t v = 0; v < nv; v++)
+        if (item_has(A, i, p[1 + v])) x |= 1u << v;
+    return (int)((w[x >> 5] >> (x & 31)) & 1u);
+}
+
 static double dist_f(const or_attrs *A, int64_t i, const or_filter *f, const int32_t *pool)
 {
+    if (f->type == OR_F_TABLE) return table_dist(A, i, f, pool);
     if (f->type == OR_F_LABEL) {
         return item_has(A, i, f->label) ? 0.0 : 1.0;
     }
@@ -627,7 +664,12 @@ static void *bf_worker(void *arg)
         int32_t nb = 0;
         int64_t valid = 0;
         for (int64_t i = 0; i < J->n; i++) {
-            if (dist_f(&J->A, i, &J->F[q], J->pool) != 0.0) continue;
+            // validity g = 1: for a table filter read the function's value
+            // directly (its distance needs a pass over all assignments)
+            const or_filter *fq = &J->F[q];
+            if (fq->type == OR_F_TABLE ? !table_true(&J->A, i, fq, J->pool)
+                                       : dist_f(&J->A, i, fq, J->pool) != 0.0)
+                continue;
             valid++;
             or_key c = {0.0, sqdist(x, J->X + (size_t)i * J->d, J->d), (int32_t)i, 0};
             /* keep the k smallest (d2, id) in a sorted array */

@@ -137,8 +137,11 @@ double label_freq(const Index &ix, int32_t l)
 }  // namespace
 
 // Encode queries [q0, q1); stops at the first bad filter (message via set_error).
+// TABLE filters write their distance table at tab_base + tpos[q] (tab_base is
+// also the address of record 0); without a table area they are rejected.
 static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0, int64_t q1,
-                               const int32_t *pool, int64_t pool_len, FilterRecord *out)
+                               const int32_t *pool, int64_t pool_len, FilterRecord *out,
+                               unsigned char *tab_base, const int64_t *tpos)
 {
     for (int64_t q = q0; q < q1; q++) {
         const jag_filter &f = F[q];
@@ -288,6 +291,59 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
                 sel += (__builtin_popcount(s) & 1) ? pr : -pr;
             }
             sel = std::min(1.0, std::max(0.0, sel));
+        } else if (f.type == F_TABLE) {
+            // general Boolean function of nvar labels (Section 3.1): the
+            // distance of assignment x is the fewest flips to a true one
+            if (!need_labels() || !check_span()) return JAG_EINVAL;
+            const int32_t *p = pool + f.off;
+            const int nv = p[0];
+            if (nv < 1 || nv > kMaxTableVars || f.len != 1 + nv + ((1 << nv) + 31) / 32) {
+                set_error("query %lld: a table filter holds nvar (1..%d), nvar labels and "
+                          "ceil(2^nvar / 32) truth-table words", (long long)q, kMaxTableVars);
+                return JAG_EINVAL;
+            }
+            for (int v = 0; v < nv; v++) {
+                int32_t l = p[1 + v];
+                if (!check_label(l)) return JAG_EINVAL;
+                for (int x = 0; x < v; x++)
+                    if (r.lits[x] == l) {
+                        set_error("query %lld: table variable label %d repeated", (long long)q, l);
+                        return JAG_EINVAL;
+                    }
+                r.lits[v] = (uint16_t)l;
+            }
+            r.nlit = nv;
+            if (!tab_base) {
+                set_error("query %lld: table filters need jag_encode_filters_sized (their distance "
+                          "tables do not fit the fixed records)", (long long)q);
+                return JAG_EINVAL;
+            }
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(p + 1 + nv);
+            uint8_t *D = tab_base + tpos[q];
+            const int N = 1 << nv;
+            for (int x = 0; x < N; x++) D[x] = ((w[x >> 5] >> (x & 31)) & 1u) ? 0 : 255;
+            // Hamming distance is a sum over variables, so one min-plus pass
+            // per variable gives the exact distance transform
+            for (int v = 0; v < nv; v++) {
+                const int b = 1 << v;
+                for (int x = 0; x < N; x++)
+                    if (!(x & b)) {
+                        int d0 = D[x], d1 = D[x | b];
+                        D[x] = (uint8_t)std::min(d0, std::min(d1 + 1, 255));
+                        D[x | b] = (uint8_t)std::min(d1, std::min(d0 + 1, 255));
+                    }
+            }
+            double pf[kMaxTableVars];
+            for (int v = 0; v < nv; v++) pf[v] = label_freq(ix, r.lits[v]);
+            sel = 0.0;
+            for (int x = 0; x < N; x++)
+                if ((w[x >> 5] >> (x & 31)) & 1u) {
+                    double pr = 1.0;
+                    for (int v = 0; v < nv; v++) pr *= ((x >> v) & 1) ? pf[v] : 1.0 - pf[v];
+                    sel += pr;
+                }
+            sel = std::min(1.0, sel);
+            r.table_off = tpos[q] - q * (int64_t)sizeof(FilterRecord);
         } else {
             set_error("query %lld: unknown filter type %d", (long long)q, f.type);
             return JAG_EINVAL;
@@ -299,22 +355,24 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
     return JAG_OK;
 }
 
-jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
-                          int64_t pool_len, FilterRecord *out)
+static jag_status run_encode(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                             int64_t pool_len, FilterRecord *out, unsigned char *tab_base,
+                             const int64_t *tpos)
 {
     // large batches are encoded by several host threads (the range
     // selectivity estimate is two binary searches over the sorted scalars)
     constexpr int64_t kPerThread = 2048;
     const int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()),
                                            std::min<int64_t>(16, nq / kPerThread));
-    if (nth <= 1) return encode_range(ix, F, 0, nq, pool, pool_len, out);
+    if (nth <= 1) return encode_range(ix, F, 0, nq, pool, pool_len, out, tab_base, tpos);
     std::vector<jag_status> st(nth, JAG_OK);
     std::vector<std::string> msg(nth);
     std::vector<std::thread> th;
     const int64_t chunk = (nq + nth - 1) / nth;
     for (int t = 0; t < nth; t++)
         th.emplace_back([&, t]() {
-            st[t] = encode_range(ix, F, t * chunk, std::min(nq, (t + 1) * chunk), pool, pool_len, out);
+            st[t] = encode_range(ix, F, t * chunk, std::min(nq, (t + 1) * chunk), pool, pool_len, out,
+                                 tab_base, tpos);
             if (st[t] != JAG_OK) msg[t] = g_err;  // the worker's own thread-local message
         });
     for (auto &x : th) x.join();
@@ -324,6 +382,56 @@ jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, cons
             return st[t];
         }
     return JAG_OK;
+}
+
+jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                          int64_t pool_len, FilterRecord *out)
+{
+    return run_encode(ix, F, nq, pool, pool_len, out, nullptr, nullptr);
+}
+
+// Byte offset of every TABLE filter's distance table from the start of the
+// encoded buffer (-1 for other filters) and the buffer's total size.
+static jag_status table_layout(const jag_filter *F, int64_t nq, const int32_t *pool, int64_t pool_len,
+                               std::vector<int64_t> *tpos, int64_t *bytes)
+{
+    int64_t at = nq * (int64_t)sizeof(FilterRecord);
+    if (tpos) tpos->assign((size_t)nq, -1);
+    for (int64_t q = 0; q < nq; q++) {
+        if (F[q].type != F_TABLE) continue;
+        const jag_filter &f = F[q];
+        if (!pool || f.off < 0 || f.len < 1 || (int64_t)f.off + f.len > pool_len || pool[f.off] < 1 ||
+            pool[f.off] > kMaxTableVars) {
+            set_error("query %lld: bad table filter span or variable count", (long long)q);
+            return JAG_EINVAL;
+        }
+        if (tpos) (*tpos)[(size_t)q] = at;
+        at += ((int64_t(1) << pool[f.off]) + 15) / 16 * 16;
+    }
+    *bytes = at;
+    return JAG_OK;
+}
+
+jag_status encoded_bytes(const Index &, const jag_filter *F, int64_t nq, const int32_t *pool, int64_t pool_len,
+                         int64_t *bytes)
+{
+    return table_layout(F, nq, pool, pool_len, nullptr, bytes);
+}
+
+jag_status encode_filters_sized(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                                int64_t pool_len, void *out, int64_t out_bytes)
+{
+    std::vector<int64_t> tpos;
+    int64_t need = 0;
+    jag_status st = table_layout(F, nq, pool, pool_len, &tpos, &need);
+    if (st != JAG_OK) return st;
+    if (out_bytes < need) {
+        set_error("encoded filters need %lld bytes, the buffer holds %lld", (long long)need,
+                  (long long)out_bytes);
+        return JAG_EINVAL;
+    }
+    unsigned char *base = static_cast<unsigned char *>(out);
+    return run_encode(ix, F, nq, pool, pool_len, reinterpret_cast<FilterRecord *>(base), base, tpos.data());
 }
 
 }  // namespace jag
@@ -550,6 +658,26 @@ jag_status jag_encode_filters(const jag_index *idx, const jag_filter *F, int64_t
     }
     return jag::encode_filters(idx->ix, F, nq, pool, pool_len,
                                static_cast<jag::FilterRecord *>(records_out));
+}
+
+jag_status jag_encoded_bytes(const jag_index *idx, const jag_filter *F, int64_t nq, const int32_t *pool,
+                             int64_t pool_len, int64_t *bytes)
+{
+    if (!idx || !bytes || nq < 0 || (nq > 0 && !F)) {
+        set_error("null argument");
+        return JAG_EINVAL;
+    }
+    return jag::encoded_bytes(idx->ix, F, nq, pool, pool_len, bytes);
+}
+
+jag_status jag_encode_filters_sized(const jag_index *idx, const jag_filter *F, int64_t nq,
+                                    const int32_t *pool, int64_t pool_len, void *out, int64_t out_bytes)
+{
+    if (!idx || nq < 0 || (nq > 0 && (!F || !out))) {
+        set_error("null argument");
+        return JAG_EINVAL;
+    }
+    return jag::encode_filters_sized(idx->ix, F, nq, pool, pool_len, out, out_bytes);
 }
 
 jag_status jag_search_encoded(jag_index *idx, const float *Q, int64_t nq, const void *records,

@@ -14,10 +14,11 @@ namespace jag {
 void set_error(const char *fmt, ...);
 
 // ---------------------------------------------------------------- filters
-enum : int32_t { F_LABEL = 0, F_RANGE = 1, F_SUBSET = 2, F_BOOLEAN = 3 };
+enum : int32_t { F_LABEL = 0, F_RANGE = 1, F_SUBSET = 2, F_BOOLEAN = 3, F_TABLE = 4 };
 
 constexpr int kMaxFilterLits = 16;
 constexpr int kMaxClauses = 8;
+constexpr int kMaxTableVars = 15;  // TABLE filters: distance table of 2^nvar bytes
 constexpr uint32_t kUnsat = 0xFFFFFFFFu;  // dist_F when no attribute can satisfy the filter
 
 // Device filter record, JAG_FILTER_RECORD_BYTES bytes, read with scalar loads.
@@ -32,7 +33,8 @@ struct alignas(16) FilterRecord {
     float selectivity;              // estimate in [0, 1]
     uint16_t lits[kMaxFilterLits];  // labels of the literals / required labels
     uint16_t clmask[kMaxClauses];   // BOOLEAN: literals of each clause (bitmask)
-    int32_t pad[12];
+    int64_t table_off;              // TABLE: byte offset from this record to its distance table
+    int32_t pad[10];
 };
 static_assert(sizeof(FilterRecord) == JAG_FILTER_RECORD_BYTES, "record size");
 
@@ -136,6 +138,13 @@ jag_status predictor_grad(const float *features, const float *targets, int64_t m
 // Host-side filter encoding with the index's selectivity estimate.
 jag_status encode_filters(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
                           int64_t pool_len, FilterRecord *out);
+// Bytes of the records of F followed by the distance tables of its TABLE
+// filters (each 2^nvar bytes, 16-byte aligned).
+jag_status encoded_bytes(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                         int64_t pool_len, int64_t *bytes);
+// Records and tables into out (at least encoded_bytes long).
+jag_status encode_filters_sized(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
+                                int64_t pool_len, void *out, int64_t out_bytes);
 
 }  // namespace jag
 

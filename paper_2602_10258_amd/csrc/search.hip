@@ -77,7 +77,9 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 // ---------------------------------------------------------------- dist_F
 // Section 3.1: label -> [label missing]; range -> distance to [lo, hi];
 // subset -> number of required labels missing; Boolean DNF -> fewest
-// literals to flip in the cheapest satisfiable clause.
+// literals to flip in the cheapest satisfiable clause; general Boolean
+// function (truth table) -> its precomputed distance table at the item's
+// assignment of the function's variables.
 // The attribute words of one item as the filter needs them: the scalar for
 // a range filter, else the label row (two uint16 labels per word, 0xFFFF
 // padded).
@@ -134,7 +136,8 @@ __device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &
                      a.W >> 1);
 }
 
-__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr &at, const SearchArgs &a)
+__device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const uint8_t *tab, const ItemAttr &at,
+                                           const SearchArgs &a)
 {
     if (f.type == F_RANGE) {
         int64_t v = at.scalar;
@@ -159,6 +162,10 @@ __device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const ItemAttr
     }
     if (f.type == F_LABEL) return (present & 1u) ? 0u : 1u;
     if (f.type == F_SUBSET) return (uint32_t)(f.nlit - __builtin_popcount(present));
+    if (f.type == F_TABLE) {  // present = the item's assignment of the table's variables
+        const uint32_t v = tab[present];
+        return v == 255u ? kUnsat : v;
+    }
     uint32_t truth = present ^ f.negmask;
     uint32_t best = kUnsat;
 #pragma unroll
@@ -569,6 +576,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const int H = a.Hmask + 1;
     Lds s = carve(smem, a.Lcap, H);
     const FilterRecord f = a.rec[q];
+    // TABLE filters: the distance table sits table_off bytes after the record
+    const uint8_t *tab = f.type == F_TABLE ? reinterpret_cast<const uint8_t *>(a.rec + q) + f.table_off : nullptr;
     const float *qv = a.Q + q * a.d;
     QueryRegs<STORE, G, CH> qr;
     qr.load(qv, a.d, lane & (G - 1));
@@ -610,7 +619,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             s.cid[0] = a.entry;
             ItemAttr at;
             load_item_attr(at, f, a.entry, a);
-            s.cdf[0] = dist_f(f, at, a);
+            s.cdf[0] = dist_f(f, tab, at, a);
         }
         __syncthreads();
         eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, 1, qr);
@@ -642,7 +651,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             load_row_attr(at, f, row, lane, a);
         }
         bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
-        uint32_t df = fresh ? dist_f(f, at, a) : 0u;
+        uint32_t df = fresh ? dist_f(f, tab, at, a) : 0u;
         nattr += __popcll(ballot64(fresh));
         if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
         uint64_t bm = ballot64(fresh);
@@ -801,6 +810,8 @@ __global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
     const int64_t q = blockIdx.x;
     Lds s = carve(smem, a.Lcap, 1);
     const FilterRecord f = a.rec[q];
+    // TABLE filters: the distance table sits table_off bytes after the record
+    const uint8_t *tab = f.type == F_TABLE ? reinterpret_cast<const uint8_t *>(a.rec + q) + f.table_off : nullptr;
     QueryRegs<JAG_STORE_F32, G, CH> qr;
     qr.load(a.Q + q * a.d, a.d, lane & (G - 1));
     int cnt = 0;
@@ -811,7 +822,7 @@ __global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
         if (ok) {
             ItemAttr at;
             load_item_attr(at, f, (int32_t)i, a);
-            df = dist_f(f, at, a);
+            df = dist_f(f, tab, at, a);
         }
         ok = ok && df == 0;
         uint64_t bm = ballot64(ok);
@@ -1480,16 +1491,19 @@ extern "C" jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t n
         jag::set_error("null argument");
         return JAG_EINVAL;
     }
-    std::vector<jag::FilterRecord> rec(nq);
-    jag_status st = jag_encode_filters(idx, F, nq, pool, pool_len, rec.data());
+    int64_t bytes = 0;
+    jag_status st = jag_encoded_bytes(idx, F, nq, pool, pool_len, &bytes);
+    if (st != JAG_OK) return st;
+    std::vector<unsigned char> rec((size_t)bytes);
+    st = jag_encode_filters_sized(idx, F, nq, pool, pool_len, rec.data(), bytes);
     if (st != JAG_OK) return st;
     void *drec = nullptr;
     hipStream_t s = (hipStream_t)stream;
-    if (hipMallocAsync(&drec, sizeof(jag::FilterRecord) * nq, s) != hipSuccess) {
+    if (hipMallocAsync(&drec, (size_t)bytes, s) != hipSuccess) {
         jag::set_error("device allocation for filter records failed");
         return JAG_ENOMEM;
     }
-    hipError_t e = hipMemcpyAsync(drec, rec.data(), sizeof(jag::FilterRecord) * nq, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(drec, rec.data(), (size_t)bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host staging buffer dies on return
     if (e != hipSuccess) {
         (void)hipFreeAsync(drec, s);

@@ -21,6 +21,7 @@ JAG_OK, JAG_EINVAL, JAG_ENOMEM, JAG_EDEVICE, JAG_EIO, JAG_EUNSUPPORTED = 0, -1, 
 STORE_F32, STORE_BF16, STORE_FP8_E4M3 = 0, 1, 2
 LABEL, RANGE, SUBSET, BOOLEAN = 0, 1, 2, 3
 ATTR_SCALAR, ATTR_LABELS, ATTR_LABELS_WEIGHTED = 0, 1, 2
+FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN, FILTER_TABLE = 0, 1, 2, 3, 4
 FILTER_RECORD_BYTES = 128
 LADDER_MAX = 16
 N_PARAMS = 5313
@@ -84,6 +85,8 @@ def lib():
             "jag_get_graph": ([P, P, P], i32),
             "jag_get_store": ([P, P, P], i32),
             "jag_encode_filters": ([P, P, i64, P, i64, P], i32),
+            "jag_encoded_bytes": ([P, P, i64, P, i64, P], i32),
+            "jag_encode_filters_sized": ([P, P, i64, P, i64, P, i64], i32),
             "jag_search_encoded": ([P, P, i64, P, i32, P, P, P, P, P], i32),
             "jag_search_batch": ([P, P, i64, P, P, i64, i32, P, P, P, P, P], i32),
             "jag_exact_knn": ([P, P, i64, P, i32, P, P, P, P], i32),
@@ -103,7 +106,8 @@ def lib():
 
 def exported_symbols() -> list[str]:
     return ["jag_build", "jag_build_graph", "jag_build_from_graph", "jag_save", "jag_load", "jag_free", "jag_info",
-            "jag_get_graph", "jag_get_store", "jag_encode_filters", "jag_search_encoded",
+            "jag_get_graph", "jag_get_store", "jag_encode_filters", "jag_encoded_bytes",
+            "jag_encode_filters_sized", "jag_search_encoded",
             "jag_search_batch", "jag_exact_knn", "jag_set_predictor", "jag_train_predictor",
             "jag_predictor_grad", "jag_last_error", "jag_version", "jag_server_start",
             "jag_server_submit", "jag_server_poll", "jag_server_drain", "jag_server_stats_get",
@@ -248,10 +252,20 @@ def jag_get_store(idx: Index):
 
 
 def jag_encode_filters(idx: Index, F, pool) -> np.ndarray:
-    """Encode int32 filter rows (type, label, lo, hi, off, len) into host records."""
+    """Encode int32 filter rows (type, label, lo, hi, off, len) into host records:
+    uint8 [nq, FILTER_RECORD_BYTES], or, when the batch holds TABLE filters, one
+    flat uint8 buffer of the records followed by their distance tables
+    (jag_encode_filters_sized)."""
     F = _np(F, np.int32)
     pool = _np(pool, np.int32)
     nq = F.shape[0]
+    if nq and np.any(F[:, 0] == FILTER_TABLE):
+        need = C.c_int64()
+        _check(lib().jag_encoded_bytes(idx.handle, _ptr(F), nq, _ptr(pool), pool.size, C.byref(need)))
+        out = np.empty(need.value, dtype=np.uint8)
+        _check(lib().jag_encode_filters_sized(idx.handle, _ptr(F), nq, _ptr(pool), pool.size, _ptr(out),
+                                              need.value))
+        return out
     out = np.empty((nq, FILTER_RECORD_BYTES), dtype=np.uint8)
     _check(lib().jag_encode_filters(idx.handle, _ptr(F), nq, _ptr(pool), pool.size, _ptr(out)))
     return out

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from workloads import FILTER_BOOLEAN, FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, encode_filters
+from workloads import FILTER_BOOLEAN, FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_TABLE, encode_filters
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -222,3 +222,65 @@ def test_weighted_label_distance_hand_worked():
     # capping as for the other kinds
     capped = O.dist_a(A, O.KIND_LABELS_WEIGHTED, u, v, 1.0)
     np.testing.assert_allclose(capped, np.maximum(got - 1.0, 0.0), atol=1e-12)
+
+
+def _table_filter(vars_, true_on):
+    tab = np.zeros(1 << len(vars_), dtype=bool)
+    tab[list(true_on)] = True
+    return encode_filters([FILTER_TABLE], [(vars_, tab)])
+
+
+def test_table_filter_hand_worked():
+    """General Boolean filter (Section 3.1) given as a truth table over labels
+    3, 1, 2 (assignment bit 0 = label 3, bit 1 = label 1, bit 2 = label 2),
+    true on assignments 0b000, 0b101 and 0b111; distances worked by hand."""
+    A = _attrs_from_sets([{1}, {3, 2}, set(), {1, 2}, {3}, {1, 2, 3}, {0}])
+    F, pool = _table_filter([3, 1, 2], [0, 5, 7])
+    d = O.dist_f(A, np.arange(7), F, np.zeros(7, dtype=np.int32), pool)
+    # {1}: x=010 -> nearest 000 (1 flip); {3,2}: x=101 true; {}: true;
+    # {1,2}: x=110 -> 111 (1); {3}: x=001 -> 000 or 101 (1); {1,2,3}: true;
+    # {0}: label 0 is not a variable, x=000 true
+    assert d.tolist() == [1, 0, 0, 1, 1, 0, 0]
+    F, pool = _table_filter([3, 1, 2], [])
+    assert np.all(O.dist_f(A, np.arange(7), F, np.zeros(7, dtype=np.int32), pool) == 2 ** 32 - 1)
+
+
+def test_table_filter_equals_dnf_distance():
+    """A DNF filter and its truth table give the same distance on every item
+    (the DNF distance is pinned above by brute force over assignments)."""
+    rng = np.random.default_rng(31)
+    n = 300
+    sets = [set(rng.choice(9, size=rng.integers(0, 6), replace=False).tolist()) for _ in range(n)]
+    A = _attrs_from_sets(sets)
+    for trial in range(40):
+        vars_ = sorted(rng.choice(9, size=rng.integers(1, 7), replace=False).tolist())
+        clauses = []
+        for _ in range(rng.integers(1, 4)):
+            m = rng.integers(1, len(vars_) + 1)
+            lits = rng.choice(vars_, size=m, replace=False).tolist()
+            clauses.append([int(l) if rng.random() < 0.6 else ~int(l) for l in lits])
+        # truth table by evaluating the DNF on each assignment of the variables
+        tab = []
+        for x in range(1 << len(vars_)):
+            held = {v for b, v in enumerate(vars_) if (x >> b) & 1}
+            tab.append(any(all((l in held) if l >= 0 else (~l not in held) for l in cl) for cl in clauses))
+        Fd, pd = encode_filters([FILTER_BOOLEAN], [clauses])
+        Ft, pt = encode_filters([FILTER_TABLE], [(vars_, np.array(tab))])
+        idx = np.arange(n)
+        dd = O.dist_f(A, idx, Fd, np.zeros(n, dtype=np.int32), pd)
+        dt = O.dist_f(A, idx, Ft, np.zeros(n, dtype=np.int32), pt)
+        assert np.array_equal(dd, dt), (trial, vars_, clauses)
+
+
+def test_table_filter_validity_in_bruteforce():
+    """The exact k-NN's validity test for table filters (the function's value)
+    agrees with distance zero."""
+    from workloads import make_config
+    w = make_config("bool15", n=3000, nq=12)
+    A = O.attrs_of(w)
+    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, 10)
+    for q in range(w.nq):
+        d = O.dist_f(A, np.arange(w.n), w.F, np.full(w.n, q, dtype=np.int32), w.pool)
+        assert nv[q] == int((d == 0).sum())
+        got = gi[q][gi[q] >= 0]
+        assert np.all(d[got] == 0)

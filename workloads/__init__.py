@@ -6,7 +6,7 @@ no distances, no filter evaluation, no graph logic.  Both the CPU oracle and
 the GPU library consume what it produces.
 """
 from .gen import (  # noqa: F401
-    FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN,
+    FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN, FILTER_TABLE,
     Workload, mixture, zipf_label_sets, range_filters, make_config,
     encode_filters, CONFIG_NAMES,
 )

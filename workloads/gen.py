@@ -15,6 +15,11 @@ Filter records are int32 rows ``(type, label, lo, hi, off, len)``:
 * BOOLEAN (3): ``pool[off:off+len]`` is a DNF program
   ``ncl, nlit_1, lit..., nlit_2, lit..., ...`` where a literal ``l >= 0``
   asks for label ``l`` and ``l < 0`` asks for the absence of label ``~l``.
+* TABLE   (4): a general Boolean function of up to 15 labels,
+  ``pool[off:off+len] = nvar, var_0..var_{nvar-1}, w_0..w_{W-1}``: the item's
+  assignment x has bit i set when it holds label ``var_i``, and the function
+  is true on x when bit ``x % 32`` of word ``w_{x // 32}`` is set
+  (W = ceil(2^nvar / 32)).
 """
 from __future__ import annotations
 
@@ -23,10 +28,10 @@ from typing import Optional
 
 import numpy as np
 
-FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN = 0, 1, 2, 3
+FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN, FILTER_TABLE = 0, 1, 2, 3, 4
 RANGE_DOMAIN = 1_000_000  # scalar attributes are uniform over [0, 10^6)
 
-CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5")
+CONFIG_NAMES = ("c1", "c2", "c3", "c4", "c5", "bool15")
 
 
 @dataclass
@@ -150,8 +155,9 @@ def range_filters(rng: np.random.Generator, nq: int, sel_lo: float = 1e-4,
 def encode_filters(kinds, payloads):
     """Build (F int32[nq,6], pool int32[*]) from per-query python descriptions.
 
-    kinds[i] in {0,1,2,3}; payloads[i] is: label (int) | (lo, hi) |
-    list of labels | list of clauses, each a list of literals.
+    kinds[i] in {0,1,2,3,4}; payloads[i] is: label (int) | (lo, hi) |
+    list of labels | list of clauses, each a list of literals |
+    (variable labels, truth table: bool array of length 2^nvar).
     """
     nq = len(kinds)
     F = np.zeros((nq, 6), dtype=np.int32)
@@ -170,6 +176,17 @@ def encode_filters(kinds, payloads):
             for cl in p:
                 prog.append(len(cl))
                 prog.extend(int(v) for v in cl)
+            F[i, 4], F[i, 5] = len(pool), len(prog)
+            pool.extend(prog)
+        elif t == FILTER_TABLE:
+            vars_, table = p
+            table = np.asarray(table, dtype=bool)
+            nv = len(vars_)
+            assert table.size == 1 << nv
+            by = np.packbits(table, bitorder="little")  # bit j of byte b = table[8b + j]
+            by = np.concatenate([by, np.zeros((-len(by)) % 4, dtype=np.uint8)])
+            words = by.view("<u4")
+            prog = [nv] + [int(v) for v in vars_] + words.view(np.int32).tolist()
             F[i, 4], F[i, 5] = len(pool), len(prog)
             pool.extend(prog)
         else:
@@ -282,6 +299,35 @@ def make_config(name: str, n: Optional[int] = None, nq: Optional[int] = None,
         del C
         return Workload("c4", base.X, Q, F, pool, scalar, loff, lab, 8, k=10, R=32, L=64,
                         meta=dict(clusters=16, thresholds="scalar{100%,1%,0}+labels{1%,0}"))
+    if name == "bool15":
+        # general Boolean filters (the paper's synthetic Boolean workload,
+        # App. D.2): every item holds a random assignment of 15 binary
+        # variables (label i present with probability 1/2), every query a
+        # random Boolean function of them whose pass rate is log-uniform in
+        # one of four ranges (2^-4, 1), (2^-8, 2^-4), (2^-12, 2^-8), (0, 2^-12)
+        n = 1_000_000 if n is None else n
+        nq = 10_000 if nq is None else nq
+        rng = np.random.default_rng(seed)
+        X, C = mixture(rng, n, 96, 256)
+        bits = rng.random((n, 15)) < 0.5
+        loff = np.zeros(n + 1, dtype=np.int64)
+        loff[1:] = np.cumsum(bits.sum(1))
+        lab = np.nonzero(bits)[1].astype(np.int32)
+        rq = np.random.default_rng(seed + 1)
+        Q, _ = mixture(rq, nq, 96, 256, centers=C)
+        kinds, pays = [], []
+        lo_exp = [(-4, 0), (-8, -4), (-12, -8), (-15, -12)]
+        for i in range(nq):
+            a, b = lo_exp[i % 4]
+            rate = 2.0 ** rq.uniform(a, b)
+            m = max(1, int(round(rate * 32768)))
+            table = np.zeros(32768, dtype=bool)
+            table[rq.choice(32768, size=m, replace=False)] = True
+            kinds.append(FILTER_TABLE)
+            pays.append((list(range(15)), table))
+        F, pool = encode_filters(kinds, pays)
+        return Workload("bool15", X, Q, F, pool, None, loff, lab, 15, k=10, R=64, L=64,
+                        meta=dict(clusters=256, thresholds="labels{100%,1%,0}"))
     if name == "c5":
         n = 10_000_000 if n is None else n
         nq = 10_000 if nq is None else nq
