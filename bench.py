@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--min-valid", type=int, default=None,
                     help="drop queries with fewer valid items (default: k for the label-set "
                          "workloads c3 and c5, else 0)")
-    ap.add_argument("--filter-type", type=int, default=None, choices=[0, 1, 2, 3],
+    ap.add_argument("--filter-type", type=int, default=None, choices=[0, 1, 2, 3, 4],
                     help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--graph-cache", default=None,
                     help="load the graph from this .npz if present, else build and save it there")
@@ -96,7 +96,7 @@ class Timer:
         return float(np.median(times))
 
 
-FILTER_NAMES = {0: "label", 1: "range", 2: "subset", 3: "boolean"}
+FILTER_NAMES = {0: "label", 1: "range", 2: "subset", 3: "boolean", 4: "boolean-table"}
 
 # beams of the fixed-beam sweeps (the kernel takes up to 1024)
 LADDER_FIXED = [10, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 56, 64, 80, 96, 128, 192, 256, 384, 512,
@@ -123,6 +123,8 @@ THRESHOLDS = {
     "c2": [(0, 1.0), (0, 0.01), (0, 0.0)],
     "c3": [(2, 1.0), (2, 0.01), (2, 0.0)],
     "c5": [(0, 1.0), (0, 0.01), (0, 0.0), (2, 0.01), (2, 0.0)],
+    # 15 binary variables as labels: |a XOR b| is the Hamming distance of assignments
+    "bool15": [(1, 1.0), (1, 0.01), (1, 0.0)],
 }
 
 
