@@ -74,6 +74,14 @@ typedef enum {
  * weight of one item's labels (meant for large, skewed label vocabularies). */
 typedef enum { JAG_ATTR_SCALAR = 0, JAG_ATTR_LABELS = 1, JAG_ATTR_LABELS_WEIGHTED = 2 } jag_attr_kind;
 
+/* Flag on a threshold-list entry's kind: a Weight-JAG entry (Section 3.4)
+ * whose comparator is w_p * dist_A(a_p, a_v) + dist(x_p, x_v) instead of the
+ * capped dist_A; `quantile` then holds the multiplier m and w_p = m * h_p,
+ * h_p = sigma / sigma_A of dist and dist_A from p to the same 500 sampled
+ * points (App. D.3).  m = 0 orders by vector distance alone; a very large m
+ * orders by attribute first. */
+#define JAG_THRESHOLD_WEIGHT 0x100
+
 /* Per-item attributes (host).  Either part may be absent (NULL). */
 typedef struct {
     const int32_t *scalar;    /* [n] int32 range attribute */
@@ -87,8 +95,8 @@ typedef struct {
  * over 500 sampled points.  quantile >= 1 means t = +inf (pure vector order),
  * quantile <= 0 means t = 0 (strict attribute order). */
 typedef struct {
-    int32_t kind;   /* jag_attr_kind */
-    float quantile; /* in [0, 1] */
+    int32_t kind;   /* jag_attr_kind, optionally | JAG_THRESHOLD_WEIGHT */
+    float quantile; /* in [0, 1]; weight entries: the multiplier m >= 0 */
 } jag_threshold;
 
 typedef struct {

@@ -40,6 +40,9 @@
 #define OR_KIND_SCALAR 0
 #define OR_KIND_LABELS 1
 #define OR_KIND_LABELS_WEIGHTED 2
+/* flag on a build entry's kind: a Weight-JAG entry (Section 3.4) whose
+ * comparator is w * dist_A + dist, with w = multiplier * h_p (below) */
+#define OR_WEIGHT_ENTRY 0x100
 
 /* dist_F of an item against a filter that no attribute can satisfy */
 #define OR_UNSAT 4294967295.0
@@ -762,18 +765,34 @@ typedef struct {
     double t;
 } da_ctx;
 
+/*
+ * First component of the build comparator of entry `kind` for base point p:
+ * Threshold-JAG, the capped dist_A(a_p, a_v; t) (Section 3.2); Weight-JAG,
+ * w * dist_A(a_p, a_v) + dist(x_p, x_v) (Section 3.4), the squared distance
+ * then breaking ties.
+ */
+static double build_first(const build_state *B, int kind, int32_t p, int32_t v, double t, double d2)
+{
+    if (kind & OR_WEIGHT_ENTRY)
+        return t * dist_a(&B->A, kind & 0xFF, p, v) + sqrt(d2);
+    return dist_a_capped(&B->A, kind, p, v, t);
+}
+
 static double first_da(const void *ctx, int32_t u)
 {
     const da_ctx *c = ctx;
-    return dist_a_capped(&c->B->A, c->kind, c->p, u, c->t);
+    double d2 = (c->kind & OR_WEIGHT_ENTRY)
+                    ? sqdist(c->B->X + (size_t)c->p * c->B->d, c->B->X + (size_t)u * c->B->d, c->B->d)
+                    : 0.0;
+    return build_first(c->B, c->kind, c->p, u, c->t, d2);
 }
 
-/* D_A^t(p, v) with the base point's threshold, then id */
+/* D_A^t(p, v) (or D_A^w) with the base point's value, then id */
 static or_key da_key(const build_state *B, int32_t p, int32_t ti, int32_t v)
 {
     or_key k;
-    k.f = dist_a_capped(&B->A, B->kinds[ti], p, v, B->thr[(size_t)p * B->nT + ti]);
     k.d2 = sqdist(B->X + (size_t)p * B->d, B->X + (size_t)v * B->d, B->d);
+    k.f = build_first(B, B->kinds[ti], p, v, B->thr[(size_t)p * B->nT + ti], k.d2);
     k.id = v;
     k.pad = 0;
     return k;
@@ -918,7 +937,30 @@ static void point_thresholds(build_state *B, const double *quant, uint64_t seed)
         for (int32_t ti = 0; ti < B->nT; ti++) {
             double q = quant[ti];
             double t;
-            if (q >= 1.0) t = INFINITY;
+            if (B->kinds[ti] & OR_WEIGHT_ENTRY) {
+                /* Weight-JAG (App. D.3): h = sigma / sigma_A, the standard
+                 * deviations of dist(x_p, x_V) and dist_A(a_p, a_V) over
+                 * the same 500 sampled points; the weight is q * h */
+                double s1 = 0.0, s2 = 0.0, a1 = 0.0, a2 = 0.0;
+                uint64_t ctr = ((uint64_t)p * 0x10000ull + (uint64_t)ti) * 4096ull;
+                int32_t m = 0;
+                for (int32_t s = 0; s < S && B->n > 1; s++) {
+                    int64_t v;
+                    do {
+                        v = (int64_t)(splitmix64(seed ^ (ctr++)) % (uint64_t)B->n);
+                    } while (v == p);
+                    double dv = sqrt(sqdist(B->X + (size_t)p * B->d, B->X + (size_t)v * B->d, B->d));
+                    double da = dist_a(&B->A, B->kinds[ti] & 0xFF, p, v);
+                    s1 += dv;
+                    s2 += dv * dv;
+                    a1 += da;
+                    a2 += da * da;
+                    m++;
+                }
+                double sd = m ? sqrt(fmax(s2 / m - (s1 / m) * (s1 / m), 0.0)) : 0.0;
+                double sa = m ? sqrt(fmax(a2 / m - (a1 / m) * (a1 / m), 0.0)) : 0.0;
+                t = sa > 0.0 ? q * sd / sa : 0.0;
+            } else if (q >= 1.0) t = INFINITY;
             else if (q <= 0.0 || B->n < 2) t = 0.0;
             else {
                 uint64_t ctr = ((uint64_t)p * 0x10000ull + (uint64_t)ti) * 4096ull;
@@ -962,7 +1004,7 @@ int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     B.A = (or_attrs){n, scalar, loff, lab, NULL, 0.0};
     double *lw = NULL;
     for (int32_t ti = 0; ti < nT; ti++)
-        if (kinds[ti] == OR_KIND_LABELS_WEIGHTED && !lw) B.A.lw = lw = label_weights(&B.A, &B.A.lw_c);
+        if ((kinds[ti] & 0xFF) == OR_KIND_LABELS_WEIGHTED && !lw) B.A.lw = lw = label_weights(&B.A, &B.A.lw_c);
     B.kinds = kinds;
     B.thr = malloc(sizeof(double) * (size_t)n * (size_t)nT);
     B.adj = adj;
@@ -1205,7 +1247,7 @@ int32_t or_prune(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     B.A = (or_attrs){n, scalar, loff, lab, NULL, 0.0};
     double *lw = NULL;
     for (int32_t ti = 0; ti < nT; ti++)
-        if (kinds[ti] == OR_KIND_LABELS_WEIGHTED && !lw) B.A.lw = lw = label_weights(&B.A, &B.A.lw_c);
+        if ((kinds[ti] & 0xFF) == OR_KIND_LABELS_WEIGHTED && !lw) B.A.lw = lw = label_weights(&B.A, &B.A.lw_c);
     B.kinds = kinds;
     B.thr = (double *)thr;
     int32_t m = joint_robust_prune(&B, p, cand, ncand, out);

@@ -24,6 +24,7 @@ _SRC = os.path.join(_HERE, "jag_oracle.c")
 _LIB = os.path.join(_HERE, "libjag_oracle.so")
 
 KIND_SCALAR, KIND_LABELS, KIND_LABELS_WEIGHTED = 0, 1, 2
+WEIGHT_ENTRY = 0x100  # flag on a build entry kind: Weight-JAG comparator, quantile = weight multiplier
 N_PARAMS = 5313
 LADDER = np.array([16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512], dtype=np.int32)
 

@@ -474,7 +474,8 @@ static jag_status make_config(const float *X, int64_t n, int32_t d, const jag_at
     cfg.max_batch = P->max_batch;
     cfg.progress = P->progress;
     for (int i = 0; i < P->n_thr; i++) {
-        int kind = P->thr[i].kind;
+        const int full = P->thr[i].kind;
+        const int kind = full & ~JAG_THRESHOLD_WEIGHT;
         if (kind == JAG_ATTR_SCALAR && !(A && A->scalar)) {
             set_error("threshold %d names scalar attributes the index does not have", i);
             return JAG_EINVAL;
@@ -491,7 +492,7 @@ static jag_status make_config(const float *X, int64_t n, int32_t d, const jag_at
             set_error("threshold %d: quantile must be >= 0", i);
             return JAG_EINVAL;
         }
-        cfg.kinds.push_back(kind);
+        cfg.kinds.push_back(full);
         cfg.quantiles.push_back(P->thr[i].quantile);
     }
     return JAG_OK;

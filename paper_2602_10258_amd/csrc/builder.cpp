@@ -123,9 +123,13 @@ struct Builder {
         }
         return (float)((A.loff[i + 1] - A.loff[i]) + (A.loff[j + 1] - A.loff[j]) - 2 * common);
     }
-    float capped(int ti, int64_t p, int64_t v) const
+    // First component of entry ti's comparator for base point p and the
+    // squared distance d2 between them: Threshold-JAG, the capped dist_A
+    // (Section 3.2); Weight-JAG, w * dist_A + dist (Section 3.4).
+    float first(int ti, int64_t p, int64_t v, float d2) const
     {
         float t = thr[(size_t)p * nT + ti];
+        if (kinds[ti] & JAG_THRESHOLD_WEIGHT) return t * dist_a(kinds[ti] & 0xFF, p, v) + std::sqrt(d2);
         if (std::isinf(t)) return 0.f;
         float x = dist_a(kinds[ti], p, v) - t;
         return x > 0.f ? x : 0.f;
@@ -164,7 +168,10 @@ void greedy_build_search(const Builder &B, Scratch &s, int64_t p, int ti)
     L.clear();
     ex.clear();
     const float *xp = B.row(p);
-    auto make = [&](int32_t u) { return Key{B.capped(ti, p, u), l2sq(xp, B.row(u), B.d), u}; };
+    auto make = [&](int32_t u) {
+        const float d2 = l2sq(xp, B.row(u), B.d);
+        return Key{B.first(ti, p, u, d2), d2, u};
+    };
     int32_t entry = B.entry;
     L.push_back(make(entry));
     ex.push_back(0);
@@ -217,7 +224,7 @@ int prune(const Builder &B, Scratch &s, int64_t p, const int32_t *V, int nv, int
     for (int j = 0; j < nv; j++) pd2[j] = l2sq(xp, B.row(V[j]), B.d);
     for (int ti = 0; ti < B.nT; ti++) {
         for (int j = 0; j < nv; j++) {
-            pf[j] = B.capped(ti, p, V[j]);
+            pf[j] = B.first(ti, p, V[j], pd2[j]);
             order[j] = j;
         }
         std::sort(order.begin(), order.end(), [&](int a, int b) {
@@ -270,7 +277,8 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
     B.alpha2 = cfg.alpha * cfg.alpha;
     B.kinds = cfg.kinds;
     int nth = cfg.n_threads > 0 ? cfg.n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
-    if (std::find(B.kinds.begin(), B.kinds.end(), (int32_t)JAG_ATTR_LABELS_WEIGHTED) != B.kinds.end()) {
+    if (std::any_of(B.kinds.begin(), B.kinds.end(),
+                    [](int32_t k) { return (k & 0xFF) == JAG_ATTR_LABELS_WEIGHTED; })) {
         // frequency-weighted label distance (App. D.3): weight log(1/p_l),
         // p_l = fraction of items holding l; C = the largest item total
         int32_t vocab = 1;
@@ -329,7 +337,30 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
         for (int ti = 0; ti < B.nT; ti++) {
             float q = cfg.quantiles[ti];
             float t;
-            if (q >= 1.f) t = std::numeric_limits<float>::infinity();
+            if (B.kinds[ti] & JAG_THRESHOLD_WEIGHT) {
+                // Weight-JAG (App. D.3): h = sigma / sigma_A over the same
+                // 500 sampled points; the weight is q * h
+                uint64_t ctr = mix64(cfg.seed * 0x100000001B3ull + (uint64_t)p * 8 + ti);
+                double s1 = 0, s2 = 0, a1 = 0, a2 = 0;
+                int m = 0;
+                for (int s = 0; s < 500 && n > 1; s++) {
+                    int64_t v;
+                    do {
+                        ctr = mix64(ctr);
+                        v = (int64_t)(ctr % (uint64_t)n);
+                    } while (v == p);
+                    double dv = std::sqrt((double)l2sq(B.row(p), B.row(v), B.d));
+                    double da = B.dist_a(B.kinds[ti] & 0xFF, p, v);
+                    s1 += dv;
+                    s2 += dv * dv;
+                    a1 += da;
+                    a2 += da * da;
+                    m++;
+                }
+                double sd = m ? std::sqrt(std::max(s2 / m - (s1 / m) * (s1 / m), 0.0)) : 0.0;
+                double sa = m ? std::sqrt(std::max(a2 / m - (a1 / m) * (a1 / m), 0.0)) : 0.0;
+                t = sa > 0.0 ? (float)(q * sd / sa) : 0.f;
+            } else if (q >= 1.f) t = std::numeric_limits<float>::infinity();
             else if (q <= 0.f || n < 2) t = 0.f;
             else {
                 uint64_t ctr = mix64(cfg.seed * 0x100000001B3ull + (uint64_t)p * 8 + ti);

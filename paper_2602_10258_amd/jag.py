@@ -22,6 +22,7 @@ STORE_F32, STORE_BF16, STORE_FP8_E4M3 = 0, 1, 2
 LABEL, RANGE, SUBSET, BOOLEAN = 0, 1, 2, 3
 ATTR_SCALAR, ATTR_LABELS, ATTR_LABELS_WEIGHTED = 0, 1, 2
 FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN, FILTER_TABLE = 0, 1, 2, 3, 4
+THRESHOLD_WEIGHT = 0x100  # flag on a threshold kind: Weight-JAG entry, quantile = weight multiplier
 FILTER_RECORD_BYTES = 128
 LADDER_MAX = 16
 N_PARAMS = 5313

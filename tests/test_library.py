@@ -118,3 +118,37 @@ def test_weighted_label_distance_builds_navigable_label_graphs():
     # measured: 0.40 with |a XOR b|, 0.79 weighted (R = 32, beam 64)
     assert rec[jag.ATTR_LABELS_WEIGHTED] >= 0.7, rec
     assert rec[jag.ATTR_LABELS_WEIGHTED] >= rec[jag.ATTR_LABELS] + 0.25, rec
+
+
+def test_host_builder_weight_entries_reach_the_threshold_limits():
+    """The product builder's Weight-JAG entries at their two limits give
+    exactly its Threshold-JAG graphs (w = 0 -> 100 %, huge w -> 0)."""
+    rng = np.random.default_rng(12)
+    n = 2000
+    X = rng.normal(0, 1, size=(n, 8)).astype(np.float32)
+    scal = rng.integers(0, 60, size=n).astype(np.int32)
+    W = jag.THRESHOLD_WEIGHT
+    kw = dict(scalar=scal, R=12, L_build=24, seed=4, n_threads=4)
+    g0, e0 = jag.jag_build_graph(X, thresholds=[(jag.ATTR_SCALAR | W, 0.0)], **kw)
+    gi, ei = jag.jag_build_graph(X, thresholds=[(jag.ATTR_SCALAR, 1.0)], **kw)
+    assert e0 == ei and np.array_equal(g0, gi)
+    gw, ew = jag.jag_build_graph(X, thresholds=[(jag.ATTR_SCALAR | W, 1e6)], **kw)
+    gz, ez = jag.jag_build_graph(X, thresholds=[(jag.ATTR_SCALAR, 0.0)], **kw)
+    assert ew == ez and np.array_equal(gw, gz)
+    with pytest.raises(jag.JagError):
+        jag.jag_build_graph(X, thresholds=[(jag.ATTR_SCALAR | 0x200, 0.0)], **kw)
+
+
+def test_weight_jag_builds_a_searchable_range_graph():
+    """Weight-JAG with the paper's range weight list {0, 10h, 1000h} gives a
+    graph the oracle's search answers range queries on well."""
+    w = make_config("c2", n=20000, nq=200)
+    W = jag.THRESHOLD_WEIGHT
+    adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, R=32, L_build=64, n_threads=8,
+                                     thresholds=[(jag.ATTR_SCALAR | W, 0.0), (jag.ATTR_SCALAR | W, 10.0),
+                                                 (jag.ATTR_SCALAR | W, 1000.0)], seed=0)
+    A = O.attrs_of(w)
+    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, 10, nthreads=8)
+    r = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, 128, 10, nthreads=8)
+    rec = float(np.nanmean(O.recall_at_k(r.ids, gi, gd, nv, 10)))
+    assert rec >= 0.9, rec

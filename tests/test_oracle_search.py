@@ -282,3 +282,34 @@ def test_build_deterministic_and_quantile_thresholds():
     deg = (a1 >= 0).sum(1)
     assert deg.max() <= 16
     assert len(_reachable(a1, e1)) >= 0.99 * 600
+
+
+def test_weight_entries_reach_the_threshold_limits():
+    """Weight-JAG entries (comparator w * dist_A + dist, Section 3.4) at their
+    two limits give exactly the Threshold-JAG graphs: w = 0 orders by vector
+    distance alone (threshold 100 %), a weight far above every vector distance
+    orders by attribute first (threshold 0)."""
+    rng = np.random.default_rng(12)
+    n = 500
+    X = rng.normal(0, 1, size=(n, 8)).astype(np.float32)
+    scal = rng.integers(0, 60, size=n).astype(np.int32)
+    sets = [sorted(rng.choice(12, size=rng.integers(1, 4), replace=False).tolist()) for _ in range(n)]
+    loff = np.zeros(n + 1, dtype=np.int64)
+    loff[1:] = np.cumsum([len(s) for s in sets])
+    lab = np.array([v for s in sets for v in s], dtype=np.int32)
+    A = O.Attrs(n, scal, loff, lab)
+    W = O.WEIGHT_ENTRY
+    for kind in (O.KIND_SCALAR, O.KIND_LABELS):
+        g0, e0, t0 = O.build(X, A, 12, 24, 1.2, [kind | W], [0.0], seed=4)
+        gi, ei, _ = O.build(X, A, 12, 24, 1.2, [kind], [1.0], seed=4)
+        assert e0 == ei and np.array_equal(g0, gi), kind
+        assert np.all(t0 == 0)
+        gw, ew, tw = O.build(X, A, 12, 24, 1.2, [kind | W], [1e6], seed=4)
+        gz, ez, _ = O.build(X, A, 12, 24, 1.2, [kind], [0.0], seed=4)
+        assert ew == ez and np.array_equal(gw, gz), kind
+        # the weight is the multiplier times sigma / sigma_A > 0
+        assert np.all(tw > 0)
+    # a middle weight gives a graph of its own, valid and searchable
+    gm, em, _ = O.build(X, A, 12, 24, 1.2, [O.KIND_SCALAR, O.KIND_SCALAR | W], [1.0, 2.0], seed=4)
+    assert (gm >= 0).sum(1).max() <= 12
+    assert len(_reachable(gm, em)) >= 0.99 * n
