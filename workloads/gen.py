@@ -315,16 +315,7 @@ def make_config(name: str, n: Optional[int] = None, nq: Optional[int] = None,
         lab = np.nonzero(bits)[1].astype(np.int32)
         rq = np.random.default_rng(seed + 1)
         Q, _ = mixture(rq, nq, 96, 256, centers=C)
-        kinds, pays = [], []
-        lo_exp = [(-4, 0), (-8, -4), (-12, -8), (-15, -12)]
-        for i in range(nq):
-            a, b = lo_exp[i % 4]
-            rate = 2.0 ** rq.uniform(a, b)
-            m = max(1, int(round(rate * 32768)))
-            table = np.zeros(32768, dtype=bool)
-            table[rq.choice(32768, size=m, replace=False)] = True
-            kinds.append(FILTER_TABLE)
-            pays.append((list(range(15)), table))
+        kinds, pays = _table_queries(rq, nq)
         F, pool = encode_filters(kinds, pays)
         return Workload("bool15", X, Q, F, pool, None, loff, lab, 15, k=10, R=64, L=64,
                         meta=dict(clusters=256, thresholds="labels{100%,1%,0}"))
@@ -366,7 +357,25 @@ def _c1_centers(seed: int) -> np.ndarray:
     return rng.normal(0.0, 4.0, size=(16, 32))
 
 
-_SHAPES = {"c1": (32, 16), "c2": (96, 256), "c3": (128, 256), "c4": (32, 16), "c5": (100, 1024)}
+_SHAPES = {"c1": (32, 16), "c2": (96, 256), "c3": (128, 256), "c4": (32, 16), "c5": (100, 1024),
+           "bool15": (96, 256)}
+
+
+def _table_queries(rq, nq: int):
+    """Random Boolean functions of 15 variables (labels 0..14), query i with
+    a pass rate log-uniform in range i % 4 of (2^-4, 1), (2^-8, 2^-4),
+    (2^-12, 2^-8), (2^-15, 2^-12); at least one true assignment."""
+    kinds, pays = [], []
+    lo_exp = [(-4, 0), (-8, -4), (-12, -8), (-15, -12)]
+    for i in range(nq):
+        a, b = lo_exp[i % 4]
+        rate = 2.0 ** rq.uniform(a, b)
+        m = max(1, int(round(rate * 32768)))
+        table = np.zeros(32768, dtype=bool)
+        table[rq.choice(32768, size=m, replace=False)] = True
+        kinds.append(FILTER_TABLE)
+        pays.append((list(range(15)), table))
+    return kinds, pays
 
 
 def extra_queries(w: Workload, nq: int, qseed: int, seed: int = 0):
@@ -385,6 +394,8 @@ def extra_queries(w: Workload, nq: int, qseed: int, seed: int = 0):
     elif w.name == "c3":
         kinds, pays = _subset_and_bool_queries(rq, nq // 2, nq - nq // 2, 1000)
         F, pool = encode_filters(kinds, pays)
+    elif w.name == "bool15":
+        F, pool = encode_filters(*_table_queries(rq, nq))
     else:
         kinds, pays = [], []
         lo, hi = range_filters(rq, nq)
