@@ -111,6 +111,14 @@ typedef struct {
     int32_t n_threads;        /* host builder threads; 0 = all hardware threads */
     int32_t max_batch;        /* cap on points inserted per parallel round; 0 = max(64, n/50) */
     int32_t progress;         /* 1 = print one line to stderr per tenth of the points inserted */
+    int32_t device;           /* 0 = rounds on host threads; 1 = rounds on the current GPU
+                                 (the same graph, edge for edge; needs L_build <= 256) */
+    const int32_t *order;     /* optional host [n]: insertion order, a permutation of 0..n-1
+                                 whose first element becomes the entry vertex; NULL = the
+                                 point nearest the centroid first, then a seeded shuffle */
+    const float *thresholds;  /* optional host [n][n_thr]: per-point t of each threshold entry
+                                 (>= 0 or +inf) or w of each weight entry (finite, >= 0);
+                                 NULL = sampled as described under jag_threshold */
 } jag_build_params;
 
 /*

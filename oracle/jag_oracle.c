@@ -986,12 +986,13 @@ static void point_thresholds(build_state *B, const double *quant, uint64_t seed)
  * Sequential JAG construction.  The entry vertex is the point nearest the
  * FP64 centroid (ties to the smaller id); it is inserted first, the other
  * points follow in a seeded random order.  Writes adj[n][R] (-1 padded) and
- * returns the entry vertex.
+ * returns the entry vertex; thr_out (the per-point thresholds) and
+ * order_out (the insertion order) are optional.
  */
 int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, const int64_t *loff,
                  const int32_t *lab, int32_t R, int32_t lb, double alpha, int32_t nT,
                  const int32_t *kinds, const double *quant, uint64_t seed, int32_t *adj,
-                 double *thr_out)
+                 double *thr_out, int32_t *order_out)
 {
     build_state B;
     B.n = n;
@@ -1052,6 +1053,7 @@ int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     for (int64_t i = 0; i < n; i++) insert_point(&B, order[i], &S, Lbuf, Vbuf, cand);
     scratch_free(&S);
     if (thr_out) memcpy(thr_out, B.thr, sizeof(double) * (size_t)n * (size_t)nT);
+    if (order_out) memcpy(order_out, order, sizeof(int32_t) * (size_t)n);
     free(Lbuf);
     free(Vbuf);
     free(cand);

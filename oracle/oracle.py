@@ -58,7 +58,7 @@ def lib():
         L.or_dist_f_pairs.restype = None
         L.or_dist_a_pairs.argtypes = [i64, P, P, P, i32, i64, P, P, f64, P]
         L.or_dist_a_pairs.restype = None
-        L.or_build.argtypes = [i64, i32, P, P, P, P, i32, i32, f64, i32, P, P, u64, P, P]
+        L.or_build.argtypes = [i64, i32, P, P, P, P, i32, i32, f64, i32, P, P, u64, P, P, P]
         L.or_build.restype = i32
         L.or_prune.argtypes = [i64, i32, P, P, P, P, i32, f64, i32, P, P, i32, P, i32, P]
         L.or_prune.restype = i32
@@ -126,9 +126,18 @@ def dist_a(attrs: Attrs, kind: int, i1, i2, t: float = 0.0) -> np.ndarray:
     return out
 
 
+def _out_i32(a: Optional[np.ndarray], n: int):
+    if a is None:
+        return None
+    if a.dtype != np.int32 or a.shape != (n,) or not a.flags.c_contiguous:
+        raise ValueError("order_out must be a contiguous int32 array of n entries")
+    return a
+
+
 def build(X, attrs: Attrs, R: int, L_build: int, alpha: float, kinds, quantiles,
-          seed: int = 0):
-    """Sequential Threshold-JAG build (Algorithms 3-4).  Returns (adj, entry, thr)."""
+          seed: int = 0, order_out: Optional[np.ndarray] = None):
+    """Sequential Threshold-JAG build (Algorithms 3-4).  Returns (adj, entry, thr);
+    the insertion order goes to order_out (int32 [n]) when given."""
     X = _c(X, np.float32)
     n, d = X.shape
     s, lo, lb = attrs.arrays()
@@ -137,7 +146,8 @@ def build(X, attrs: Attrs, R: int, L_build: int, alpha: float, kinds, quantiles,
     adj = np.empty((n, R), dtype=np.int32)
     thr = np.empty((n, len(kinds)), dtype=np.float64)
     entry = lib().or_build(n, d, _p(X), _p(s), _p(lo), _p(lb), R, L_build, float(alpha),
-                           len(kinds), _p(kinds), _p(quant), seed, _p(adj), _p(thr))
+                           len(kinds), _p(kinds), _p(quant), seed, _p(adj), _p(thr),
+                           _p(_out_i32(order_out, n)))
     return adj, int(entry), thr
 
 

@@ -495,6 +495,44 @@ static jag_status make_config(const float *X, int64_t n, int32_t d, const jag_at
         cfg.kinds.push_back(full);
         cfg.quantiles.push_back(P->thr[i].quantile);
     }
+    if (P->device != 0 && P->device != 1) {
+        set_error("device must be 0 (host threads) or 1 (GPU)");
+        return JAG_EINVAL;
+    }
+    cfg.device = P->device;
+    if (P->order) {
+        std::vector<char> hit((size_t)n, 0);
+        for (int64_t i = 0; i < n; i++) {
+            const int32_t v = P->order[i];
+            if (v < 0 || v >= n || hit[(size_t)v]) {
+                set_error("order is not a permutation of 0..n-1 (position %lld)", (long long)i);
+                return JAG_EINVAL;
+            }
+            hit[(size_t)v] = 1;
+        }
+        cfg.order = P->order;
+    }
+    if (P->thresholds) {
+        for (int64_t i = 0; i < n * (int64_t)P->n_thr; i++) {
+            const float t = P->thresholds[i];
+            const bool weight = (P->thr[i % P->n_thr].kind & JAG_THRESHOLD_WEIGHT) != 0;
+            if (!(t >= 0.f) || (weight && std::isinf(t))) {
+                set_error("thresholds[%lld] = %g is not a valid %s", (long long)i, (double)t,
+                          weight ? "weight (finite, >= 0)" : "threshold (>= 0 or +inf)");
+                return JAG_EINVAL;
+            }
+        }
+        cfg.thresholds = P->thresholds;
+    }
+    return JAG_OK;
+}
+
+// The graph of cfg on host threads or on the current device.
+static jag_status run_build(const float *X, int64_t n, int32_t d, const jag::AttrView &av,
+                            const jag::BuildConfig &cfg, std::vector<int32_t> &adj, int32_t &entry)
+{
+    if (cfg.device) return jag::build_graph_device(X, n, d, av, cfg, adj, entry);
+    jag::build_graph(X, n, d, av, cfg, adj, entry);
     return JAG_OK;
 }
 
@@ -511,7 +549,8 @@ jag_status jag_build_graph(const float *X, int64_t n, int32_t d, const jag_attrs
     try {
         jag::AttrView av{n, A ? A->scalar : nullptr, A ? A->label_off : nullptr, A ? A->labels : nullptr};
         std::vector<int32_t> adj;
-        jag::build_graph(X, n, d, av, cfg, adj, *entry);
+        st = run_build(X, n, d, av, cfg, adj, *entry);
+        if (st != JAG_OK) return st;
         std::memcpy(adj_out, adj.data(), adj.size() * sizeof(int32_t));
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
@@ -543,7 +582,8 @@ jag_status jag_build(const float *X, int64_t n, int32_t d, const jag_attrs *A,
         jag::AttrView av{n, ix.has_scalar ? ix.scalar.data() : nullptr,
                          ix.has_labels ? ix.loff.data() : nullptr,
                          ix.has_labels ? ix.lab.data() : nullptr};
-        jag::build_graph(ix.X.data(), n, d, av, cfg, ix.adj, ix.entry);
+        st = run_build(ix.X.data(), n, d, av, cfg, ix.adj, ix.entry);
+        if (st != JAG_OK) return st;
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return JAG_ENOMEM;

@@ -31,15 +31,40 @@ inline uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+}  // namespace
+
+// Squared Euclidean distance in the library's fixed FP32 order: partial sum
+// k (0..31) takes the elements i = k mod 32 with one fused multiply-add each;
+// the 32 partials fold as ((s0 + s1) + (s2 + s3)) per group of four, then the
+// eight group sums pairwise at strides 4, 2 and 1.  The device builder reads
+// a row as eight float4 per 32 elements (lane g of 8 holds partials 4g..4g+3)
+// and folds across lanes in the same order, so both give identical bits.
+float l2sq_canonical(const float *__restrict a, const float *__restrict b, int d)
+{
+    float acc[32] = {};
+    int i = 0;
+    for (; i + 32 <= d; i += 32)
+        for (int k = 0; k < 32; k++) {
+            const float t = a[i + k] - b[i + k];
+            acc[k] = std::fma(t, t, acc[k]);
+        }
+    for (int k = 0; i + k < d; k++) {
+        const float t = a[i + k] - b[i + k];
+        acc[k] = std::fma(t, t, acc[k]);
+    }
+    float u[8];
+    for (int g = 0; g < 8; g++) u[g] = (acc[4 * g] + acc[4 * g + 1]) + (acc[4 * g + 2] + acc[4 * g + 3]);
+    float v[4];
+    for (int g = 0; g < 4; g++) v[g] = u[g] + u[g + 4];
+    const float w0 = v[0] + v[2], w1 = v[1] + v[3];
+    return w0 + w1;
+}
+
+namespace {
+
 inline float l2sq(const float *__restrict a, const float *__restrict b, int d)
 {
-    float s = 0.f;
-#pragma omp simd reduction(+ : s)
-    for (int i = 0; i < d; i++) {
-        float t = a[i] - b[i];
-        s += t * t;
-    }
-    return s;
+    return l2sq_canonical(a, b, d);
 }
 
 void parallel_for(int64_t n, int nthreads, const std::function<void(int64_t, int)> &fn,
@@ -78,62 +103,64 @@ inline bool key_lt(const Key &a, const Key &b)
     return a.id < b.id;
 }
 
-struct Builder {
-    const float *X;
-    int64_t n;
-    int d;
-    AttrView A;
-    int R, lb, nT, cap;
-    int32_t entry = 0;
-    float alpha2;
-    std::vector<int32_t> kinds;
-    std::vector<float> thr;  // [n][nT]
-    std::vector<int32_t> adj;
-    std::vector<int32_t> deg;
-    std::vector<float> lw;  // weighted labels: log(1/p_l) per label
-    float lw_c = 0.f;       // and the constant C
-
-    float dist_a(int kind, int64_t i, int64_t j) const
-    {
-        if (kind == JAG_ATTR_SCALAR) return std::fabs((float)((int64_t)A.scalar[i] - (int64_t)A.scalar[j]));
-        if (kind == JAG_ATTR_LABELS_WEIGHTED) {
-            // C minus the weight of the shared labels (merge of the sorted rows)
-            int64_t x = A.loff[i], xe = A.loff[i + 1], y = A.loff[j], ye = A.loff[j + 1];
-            float shared = 0.f;
-            while (x < xe && y < ye) {
-                if (A.lab[x] == A.lab[y]) {
-                    shared += lw[A.lab[x]];
-                    x++;
-                    y++;
-                } else if (A.lab[x] < A.lab[y]) x++;
-                else y++;
-            }
-            return lw_c - shared;
-        }
-        // |a_i XOR a_j| by merging the two sorted rows
-        int64_t x = A.loff[i], xe = A.loff[i + 1], y = A.loff[j], ye = A.loff[j + 1];
-        int64_t common = 0;
+// dist_A(a_i, a_j) of an attribute kind (Section 3.1; App. D.3 for the
+// frequency-weighted label distance), in FP32 as the device builder computes it.
+float dist_a_host(const AttrView &A, const BuildPlan &P, int kind, int64_t i, int64_t j)
+{
+    if (kind == JAG_ATTR_SCALAR) return std::fabs((float)((int64_t)A.scalar[i] - (int64_t)A.scalar[j]));
+    int64_t x = A.loff[i], xe = A.loff[i + 1], y = A.loff[j], ye = A.loff[j + 1];
+    if (kind == JAG_ATTR_LABELS_WEIGHTED) {
+        // C minus the weight of the shared labels (merge of the sorted rows)
+        float shared = 0.f;
         while (x < xe && y < ye) {
             if (A.lab[x] == A.lab[y]) {
-                common++;
+                shared += P.lw[(size_t)A.lab[x]];
                 x++;
                 y++;
             } else if (A.lab[x] < A.lab[y]) x++;
             else y++;
         }
-        return (float)((A.loff[i + 1] - A.loff[i]) + (A.loff[j + 1] - A.loff[j]) - 2 * common);
+        return P.lw_c - shared;
     }
-    // First component of entry ti's comparator for base point p and the
-    // squared distance d2 between them: Threshold-JAG, the capped dist_A
-    // (Section 3.2); Weight-JAG, w * dist_A + dist (Section 3.4).
-    float first(int ti, int64_t p, int64_t v, float d2) const
-    {
-        float t = thr[(size_t)p * nT + ti];
-        if (kinds[ti] & JAG_THRESHOLD_WEIGHT) return t * dist_a(kinds[ti] & 0xFF, p, v) + std::sqrt(d2);
-        if (std::isinf(t)) return 0.f;
-        float x = dist_a(kinds[ti], p, v) - t;
-        return x > 0.f ? x : 0.f;
+    // |a_i XOR a_j| by merging the two sorted rows
+    int64_t common = 0;
+    while (x < xe && y < ye) {
+        if (A.lab[x] == A.lab[y]) {
+            common++;
+            x++;
+            y++;
+        } else if (A.lab[x] < A.lab[y]) x++;
+        else y++;
     }
+    return (float)((A.loff[i + 1] - A.loff[i]) + (A.loff[j + 1] - A.loff[j]) - 2 * common);
+}
+
+// First component of entry ti's comparator for base point p and the squared
+// distance d2 between them: Threshold-JAG, the capped dist_A (Section 3.2);
+// Weight-JAG, w * dist_A + dist with one rounding of the product-sum (Section 3.4).
+float first_host(const AttrView &A, const BuildPlan &P, int ti, int64_t p, int64_t v, float d2)
+{
+    const float t = P.thr[(size_t)p * P.nT + ti];
+    const int kind = P.kinds[ti];
+    if (kind & JAG_THRESHOLD_WEIGHT) return std::fma(t, dist_a_host(A, P, kind & 0xFF, p, v), std::sqrt(d2));
+    if (std::isinf(t)) return 0.f;
+    const float x = dist_a_host(A, P, kind, p, v) - t;
+    return x > 0.f ? x : 0.f;
+}
+
+struct Builder {
+    const float *X;
+    int64_t n;
+    int d;
+    AttrView A;
+    const BuildPlan *P;
+    int R, lb, nT, cap, hopcap;
+    float alpha2;
+    std::vector<int32_t> adj;
+    std::vector<int32_t> deg;
+
+    float dist_a(int kind, int64_t i, int64_t j) const { return dist_a_host(A, *P, kind, i, j); }
+    float first(int ti, int64_t p, int64_t v, float d2) const { return first_host(A, *P, ti, p, v, d2); }
     const float *row(int64_t i) const { return X + (size_t)i * d; }
 };
 
@@ -155,7 +182,9 @@ struct Scratch {
 // GreedySearch(G, x_p, 1, l_b, D_A^t) over the frozen graph; appends the
 // expanded vertices to s.visited.  A vertex seen earlier in this search is
 // not re-evaluated: the beam always holds the l_b best vertices discovered,
-// so one that fell out can never get back in.
+// so one that fell out can never get back in.  At most hopcap = 4 l_b
+// expansions (a bound the searches stay far below; it sizes the device
+// builder's candidate buffers).
 void greedy_build_search(const Builder &B, Scratch &s, int64_t p, int ti)
 {
     if (++s.epoch == 0) {
@@ -172,14 +201,16 @@ void greedy_build_search(const Builder &B, Scratch &s, int64_t p, int ti)
         const float d2 = l2sq(xp, B.row(u), B.d);
         return Key{B.first(ti, p, u, d2), d2, u};
     };
-    int32_t entry = B.entry;
+    int32_t entry = B.P->entry;
     L.push_back(make(entry));
     ex.push_back(0);
     s.seen[entry] = ep;
     size_t hint = 0;
+    int hops = 0;
     for (;;) {
         while (hint < L.size() && ex[hint]) hint++;
-        if (hint >= L.size()) break;
+        if (hint >= L.size() || hops >= B.hopcap) break;
+        hops++;
         size_t pi = hint;
         ex[pi] = 1;
         int32_t v = L[pi].id;
@@ -262,47 +293,51 @@ int prune(const Builder &B, Scratch &s, int64_t p, const int32_t *V, int nv, int
 
 }  // namespace
 
-int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
-                std::vector<int32_t> &adj, int32_t &entry)
+int plan_build(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
+               BuildPlan &P)
 {
-    Builder B;
-    B.X = X;
-    B.n = n;
-    B.d = d;
-    B.A = A;
-    B.R = cfg.R;
-    B.lb = cfg.L_build > 0 ? cfg.L_build : 2 * cfg.R;
-    B.nT = (int)cfg.kinds.size();
-    B.cap = (9 * B.R + 10 * B.nT - 1) / (10 * B.nT);
-    B.alpha2 = cfg.alpha * cfg.alpha;
-    B.kinds = cfg.kinds;
-    int nth = cfg.n_threads > 0 ? cfg.n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
-    if (std::any_of(B.kinds.begin(), B.kinds.end(),
+    P.R = cfg.R;
+    P.lb = cfg.L_build > 0 ? cfg.L_build : 2 * cfg.R;
+    P.nT = (int)cfg.kinds.size();
+    P.cap = (9 * P.R + 10 * P.nT - 1) / (10 * P.nT);
+    P.hopcap = 4 * P.lb;
+    P.alpha2 = cfg.alpha * cfg.alpha;
+    P.kinds = cfg.kinds;
+    P.max_batch = cfg.max_batch > 0 ? cfg.max_batch : std::max<int64_t>(64, n / 50);
+    const int nth = cfg.n_threads > 0 ? cfg.n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    P.lw.clear();
+    P.lw_c = 0.f;
+    if (std::any_of(P.kinds.begin(), P.kinds.end(),
                     [](int32_t k) { return (k & 0xFF) == JAG_ATTR_LABELS_WEIGHTED; })) {
         // frequency-weighted label distance (App. D.3): weight log(1/p_l),
-        // p_l = fraction of items holding l; C = the largest item total
+        // p_l = fraction of items holding l; C = the largest item total, summed
+        // in FP32 in label order like the shared weights, so that no distance
+        // falls below zero
         int32_t vocab = 1;
         for (int64_t x = 0; x < A.loff[n]; x++) vocab = std::max(vocab, A.lab[x] + 1);
         std::vector<double> cnt((size_t)vocab, 0.0);
         for (int64_t x = 0; x < A.loff[n]; x++) cnt[(size_t)A.lab[x]] += 1.0;
-        B.lw.assign(cnt.size(), 0.f);
+        P.lw.assign(cnt.size(), 0.f);
         for (size_t l = 0; l < cnt.size(); l++)
-            B.lw[l] = cnt[l] > 0.0 ? (float)std::log((double)n / cnt[l]) : 0.f;
-        double c = 0.0;
+            P.lw[l] = cnt[l] > 0.0 ? (float)std::log((double)n / cnt[l]) : 0.f;
+        float c = 0.f;
         for (int64_t i = 0; i < n; i++) {
-            double t = 0.0;
-            for (int64_t x = A.loff[i]; x < A.loff[i + 1]; x++) t += B.lw[(size_t)A.lab[x]];
+            float t = 0.f;
+            for (int64_t x = A.loff[i]; x < A.loff[i + 1]; x++) t += P.lw[(size_t)A.lab[x]];
             c = std::max(c, t);
         }
-        B.lw_c = (float)c;
+        P.lw_c = c;
     }
 
-    // entry vertex: nearest to the FP64 centroid, smaller id on ties
-    std::vector<double> cen(d, 0.0);
-    for (int64_t i = 0; i < n; i++)
-        for (int j = 0; j < d; j++) cen[j] += X[(size_t)i * d + j];
-    for (int j = 0; j < d; j++) cen[j] /= (double)n;
-    {
+    if (cfg.order) {
+        P.order.assign(cfg.order, cfg.order + n);
+        P.entry = P.order[0];
+    } else {
+        // entry vertex: nearest to the FP64 centroid, smaller id on ties
+        std::vector<double> cen(d, 0.0);
+        for (int64_t i = 0; i < n; i++)
+            for (int j = 0; j < d; j++) cen[j] += X[(size_t)i * d + j];
+        for (int j = 0; j < d; j++) cen[j] /= (double)n;
         std::vector<double> best(nth, std::numeric_limits<double>::infinity());
         std::vector<int64_t> bid(nth, -1);
         int64_t chunk = (n + nth - 1) / nth;
@@ -326,18 +361,34 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
                 be = best[t];
                 e = bid[t];
             }
-        entry = (int32_t)e;
-        B.entry = entry;
+        P.entry = (int32_t)e;
+        // insertion order: entry first, then a seeded permutation
+        P.order.clear();
+        P.order.reserve(n);
+        P.order.push_back(P.entry);
+        for (int64_t i = 0; i < n; i++)
+            if (i != P.entry) P.order.push_back((int32_t)i);
+        uint64_t st = mix64(cfg.seed ^ 0xC0FFEEull);
+        for (int64_t i = n - 1; i > 1; i--) {
+            st = mix64(st);
+            int64_t j = 1 + (int64_t)(st % (uint64_t)i);
+            std::swap(P.order[i], P.order[j]);
+        }
     }
 
+    if (cfg.thresholds) {
+        P.thr.assign(cfg.thresholds, cfg.thresholds + (size_t)n * P.nT);
+        return 0;
+    }
     // per-point thresholds: nearest-rank quantile of dist_A over 500 samples
-    B.thr.assign((size_t)n * B.nT, 0.f);
+    P.thr.assign((size_t)n * P.nT, 0.f);
     parallel_for(n, nth, [&](int64_t p, int) {
         float vals[500];
-        for (int ti = 0; ti < B.nT; ti++) {
+        const float *xp = X + (size_t)p * d;
+        for (int ti = 0; ti < P.nT; ti++) {
             float q = cfg.quantiles[ti];
             float t;
-            if (B.kinds[ti] & JAG_THRESHOLD_WEIGHT) {
+            if (P.kinds[ti] & JAG_THRESHOLD_WEIGHT) {
                 // Weight-JAG (App. D.3): h = sigma / sigma_A over the same
                 // 500 sampled points; the weight is q * h
                 uint64_t ctr = mix64(cfg.seed * 0x100000001B3ull + (uint64_t)p * 8 + ti);
@@ -349,8 +400,8 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
                         ctr = mix64(ctr);
                         v = (int64_t)(ctr % (uint64_t)n);
                     } while (v == p);
-                    double dv = std::sqrt((double)l2sq(B.row(p), B.row(v), B.d));
-                    double da = B.dist_a(B.kinds[ti] & 0xFF, p, v);
+                    double dv = std::sqrt((double)l2sq(xp, X + (size_t)v * d, d));
+                    double da = dist_a_host(A, P, P.kinds[ti] & 0xFF, p, v);
                     s1 += dv;
                     s2 += dv * dv;
                     a1 += da;
@@ -370,37 +421,45 @@ int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const B
                         ctr = mix64(ctr);
                         v = (int64_t)(ctr % (uint64_t)n);
                     } while (v == p);
-                    vals[s] = B.dist_a(B.kinds[ti], p, v);
+                    vals[s] = dist_a_host(A, P, P.kinds[ti], p, v);
                 }
                 int r = (int)std::ceil((double)q * 500.0);
                 r = std::max(1, std::min(500, r));
                 std::nth_element(vals, vals + (r - 1), vals + 500);
                 t = vals[r - 1];
             }
-            B.thr[(size_t)p * B.nT + ti] = t;
+            P.thr[(size_t)p * P.nT + ti] = t;
         }
     }, 256);
+    return 0;
+}
 
-    // insertion order: entry first, then a seeded permutation
-    std::vector<int32_t> order;
-    order.reserve(n);
-    order.push_back(entry);
-    for (int64_t i = 0; i < n; i++)
-        if (i != entry) order.push_back((int32_t)i);
-    {
-        uint64_t st = mix64(cfg.seed ^ 0xC0FFEEull);
-        for (int64_t i = n - 1; i > 1; i--) {
-            st = mix64(st);
-            int64_t j = 1 + (int64_t)(st % (uint64_t)i);
-            std::swap(order[i], order[j]);
-        }
-    }
+int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
+                std::vector<int32_t> &adj, int32_t &entry)
+{
+    BuildPlan plan;
+    plan_build(X, n, d, A, cfg, plan);
+    entry = plan.entry;
+    Builder B;
+    B.X = X;
+    B.n = n;
+    B.d = d;
+    B.A = A;
+    B.P = &plan;
+    B.R = plan.R;
+    B.lb = plan.lb;
+    B.nT = plan.nT;
+    B.cap = plan.cap;
+    B.hopcap = plan.hopcap;
+    B.alpha2 = plan.alpha2;
+    const int nth = cfg.n_threads > 0 ? cfg.n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    const std::vector<int32_t> &order = plan.order;
 
     B.adj.assign((size_t)n * B.R, -1);
     B.deg.assign(n, 0);
     std::vector<Scratch> scr(nth);
     for (auto &s : scr) s.seen.assign(n, 0);
-    int64_t max_batch = cfg.max_batch > 0 ? cfg.max_batch : std::max<int64_t>(64, n / 50);
+    const int64_t max_batch = plan.max_batch;
     std::vector<std::vector<int32_t>> newrow;
     int64_t pos = 1;  // order[0] = entry, inserted with no out-edges
     int64_t bs = 1;

@@ -97,6 +97,24 @@ struct BuildConfig {
     int32_t n_threads = 0;
     int32_t max_batch = 0;
     int32_t progress = 0;
+    int32_t device = 0;                 // 1: rounds run on the current GPU
+    const int32_t *order = nullptr;     // optional insertion order (order[0] = entry)
+    const float *thresholds = nullptr;  // optional per-point t / w values [n][|T|]
+};
+
+// What both builders need before the first insertion: comparator entries,
+// per-point threshold (or weight) values, the insertion order with the entry
+// vertex first, and the label weights of the weighted label distance.
+struct BuildPlan {
+    int32_t R = 0, lb = 0, nT = 0, cap = 0, hopcap = 0;
+    float alpha2 = 0.f;
+    int32_t entry = 0;
+    int64_t max_batch = 0;
+    std::vector<int32_t> kinds;
+    std::vector<float> thr;      // [n][nT]
+    std::vector<int32_t> order;  // [n]
+    std::vector<float> lw;       // log(1/p_l) per label (weighted labels only)
+    float lw_c = 0.f;            // the constant C of the weighted label distance
 };
 
 struct AttrView {
@@ -106,9 +124,20 @@ struct AttrView {
     const int32_t *lab = nullptr;
 };
 
+int plan_build(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
+               BuildPlan &plan);
+
+// Squared distance in the fixed FP32 order shared by the host and device builders.
+float l2sq_canonical(const float *a, const float *b, int d);
+
 // Threshold-JAG construction on host threads; fills adj[n*R] (-1 padded).
 int build_graph(const float *X, int64_t n, int32_t d, const AttrView &A, const BuildConfig &cfg,
                 std::vector<int32_t> &adj, int32_t &entry);
+
+// The same construction with the rounds on the current device: the same
+// graph as build_graph, edge for edge.
+jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrView &A,
+                              const BuildConfig &cfg, std::vector<int32_t> &adj, int32_t &entry);
 
 // ---------------------------------------------------------------- device side
 // All of these run on the calling thread's current device and report errors

@@ -47,7 +47,8 @@ class jag_build_params(C.Structure):
     _fields_ = [("R", C.c_int32), ("L_build", C.c_int32), ("alpha", C.c_float),
                 ("n_thr", C.c_int32), ("thr", C.POINTER(jag_threshold)), ("store", C.c_int32),
                 ("keep_f32", C.c_int32), ("seed", C.c_uint64), ("n_threads", C.c_int32),
-                ("max_batch", C.c_int32), ("progress", C.c_int32)]
+                ("max_batch", C.c_int32), ("progress", C.c_int32), ("device", C.c_int32),
+                ("order", C.c_void_p), ("thresholds", C.c_void_p)]
 
 
 class jag_search_params(C.Structure):
@@ -147,12 +148,25 @@ def _attrs(scalar, label_off, labels, vocab):
     return a, keep
 
 
-def _params(R, L_build, alpha, thresholds, store, keep_f32, seed, n_threads, max_batch, progress=False):
+def _params(R, L_build, alpha, thresholds, store, keep_f32, seed, n_threads, max_batch, progress=False,
+            device=False, order=None, thr_values=None):
+    """jag_build_params and the buffers it points to (keep them alive with it)."""
     thr = (jag_threshold * max(1, len(thresholds)))(*[jag_threshold(int(k), float(q)) for k, q in thresholds])
+    order = _np(order, np.int32)
+    thr_values = _np(thr_values, np.float32)
     p = jag_build_params(int(R), int(L_build), float(alpha), len(thresholds),
                          C.cast(thr, C.POINTER(jag_threshold)), int(store), int(keep_f32),
-                         int(seed), int(n_threads), int(max_batch), int(bool(progress)))
-    return p, thr
+                         int(seed), int(n_threads), int(max_batch), int(bool(progress)),
+                         int(bool(device)), _ptr(order), _ptr(thr_values))
+    return p, (thr, order, thr_values)
+
+
+def _check_plan_inputs(n, nthr, order, thr_values):
+    """The C ABI cannot see array lengths: check them here."""
+    if order is not None and np.shape(order) != (n,):
+        raise ValueError(f"order must have shape ({n},)")
+    if thr_values is not None and np.shape(thr_values) != (n, nthr):
+        raise ValueError(f"thr_values must have shape ({n}, {nthr})")
 
 
 class Index:
@@ -186,10 +200,12 @@ class Index:
 
 def jag_build(X, scalar=None, label_off=None, labels=None, vocab=0, R=32, L_build=0, alpha=1.2,
               thresholds: Sequence = ((ATTR_SCALAR, 1.0),), store=STORE_F32, keep_f32=False,
-              seed=0, n_threads=0, max_batch=0) -> Index:
+              seed=0, n_threads=0, max_batch=0, device=False, order=None, thr_values=None) -> Index:
     X = _np(X, np.float32)
+    _check_plan_inputs(X.shape[0], len(thresholds), order, thr_values)
     a, keep = _attrs(scalar, label_off, labels, vocab)
-    p, thr = _params(R, L_build, alpha, thresholds, store, keep_f32, seed, n_threads, max_batch)
+    p, thr = _params(R, L_build, alpha, thresholds, store, keep_f32, seed, n_threads, max_batch,
+                     False, device, order, thr_values)
     h = C.c_void_p()
     _check(lib().jag_build(_ptr(X), X.shape[0], X.shape[1], C.byref(a), C.byref(p), C.byref(h)))
     return Index(h)
@@ -197,11 +213,16 @@ def jag_build(X, scalar=None, label_off=None, labels=None, vocab=0, R=32, L_buil
 
 def jag_build_graph(X, scalar=None, label_off=None, labels=None, vocab=0, R=32, L_build=0,
                     alpha=1.2, thresholds: Sequence = ((ATTR_SCALAR, 1.0),), seed=0, n_threads=0,
-                    max_batch=0, progress=False):
-    """Host-only Threshold-JAG construction; returns (adj int32[n, R], entry)."""
+                    max_batch=0, progress=False, device=False, order=None, thr_values=None):
+    """Threshold-/Weight-JAG construction on host threads (device=False) or on
+    the current GPU (device=True, the same graph); returns (adj int32[n, R], entry).
+    order: optional insertion order (order[0] becomes the entry vertex);
+    thr_values: optional float32 [n, len(thresholds)] per-point t / w values."""
     X = _np(X, np.float32)
+    _check_plan_inputs(X.shape[0], len(thresholds), order, thr_values)
     a, keep = _attrs(scalar, label_off, labels, vocab)
-    p, thr = _params(R, L_build, alpha, thresholds, STORE_F32, 0, seed, n_threads, max_batch, progress)
+    p, thr = _params(R, L_build, alpha, thresholds, STORE_F32, 0, seed, n_threads, max_batch, progress,
+                     device, order, thr_values)
     adj = np.empty((X.shape[0], R), dtype=np.int32)
     e = C.c_int32()
     _check(lib().jag_build_graph(_ptr(X), X.shape[0], X.shape[1], C.byref(a), C.byref(p), _ptr(adj),

@@ -1,0 +1,83 @@
+"""The library's graph builder against the oracle's (Algorithms 3 and 4 with
+the App. D.3 notes; Section 3.4 for weight entries).
+
+In rounds of one point, with the oracle's insertion order and per-point
+thresholds handed in, the library's builder performs exactly the oracle's
+sequential construction, so the two graphs must agree edge for edge (the
+library in FP32, the oracle in FP64: the small worlds here have no ties
+closer than FP32 rounding).  The frequency-weighted label distance is left
+out: its constant C is an FP32 sum in the library and an FP64 sum in the
+oracle, which moves every capped distance by a rounding-sized amount."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2602_10258_amd import jag
+
+W = jag.THRESHOLD_WEIGHT
+S, LB = jag.ATTR_SCALAR, jag.ATTR_LABELS
+
+CASES = {
+    "scalar": (400, 16, 12, 24, [(S, 1.0), (S, 0.05), (S, 0.0)]),
+    "labels": (400, 16, 12, 24, [(LB, 1.0), (LB, 0.1), (LB, 0.0)]),
+    "mixed5": (1000, 33, 10, 20, [(S, 1.0), (LB, 0.1), (S, 0.0), (LB, 0.0), (S, 0.2)]),
+    "weight": (400, 16, 12, 24, [(S | W, 0.0), (S | W, 2.0), (S | W, 50.0)]),
+    "wide": (1500, 40, 20, 40, [(S, 1.0), (S, 0.01), (S, 0.0)]),
+}
+
+
+def small_world(n, d, seed, vocab=12):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    scal = rng.integers(0, 10**6, size=n).astype(np.int32)
+    nl = rng.integers(1, 5, size=n)
+    loff = np.zeros(n + 1, np.int64)
+    loff[1:] = np.cumsum(nl)
+    lab = np.concatenate([np.sort(rng.choice(vocab, size=k, replace=False)) for k in nl]).astype(np.int32)
+    return X, scal, loff, lab
+
+
+def oracle_graph(X, scal, loff, lab, R, lb, thr, seed):
+    n = X.shape[0]
+    A = O.Attrs(n, scal, loff, lab)
+    order = np.empty(n, np.int32)
+    adj, entry, tv = O.build(X, A, R, lb, 1.2, [k for k, _ in thr], [q for _, q in thr], seed=seed,
+                             order_out=order)
+    return adj, entry, tv.astype(np.float32), order
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_sequential_rounds_give_the_oracle_graph(case):
+    n, d, R, lb, thr = CASES[case]
+    X, scal, loff, lab = small_world(n, d, seed=len(case))
+    oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, R, lb, thr, seed=3)
+    assert order[0] == oentry
+    adj, entry = jag.jag_build_graph(X, scalar=scal, label_off=loff, labels=lab, vocab=12, R=R, L_build=lb,
+                                     thresholds=thr, max_batch=1, order=order, thr_values=tv, n_threads=4)
+    assert entry == oentry
+    assert np.array_equal(adj, oadj), f"{np.sum(np.any(adj != oadj, axis=1))} rows differ"
+
+
+def test_given_order_and_thresholds_are_checked():
+    X, scal, loff, lab = small_world(50, 8, seed=1)
+    thr = [(S, 1.0), (S | W, 1.0)]
+    kw = dict(scalar=scal, R=8, thresholds=thr, n_threads=2)
+    bad_order = np.arange(50, dtype=np.int32)
+    bad_order[3] = 4
+    with pytest.raises(jag.JagError):
+        jag.jag_build_graph(X, order=bad_order, **kw)
+    tv = np.zeros((50, 2), np.float32)
+    tv[:, 0] = np.inf
+    adj, entry = jag.jag_build_graph(X, order=np.arange(50, dtype=np.int32)[::-1].copy(), thr_values=tv, **kw)
+    assert entry == 49
+    for bad in (np.nan, -1.0):
+        tb = tv.copy()
+        tb[7, 0] = bad
+        with pytest.raises(jag.JagError):
+            jag.jag_build_graph(X, thr_values=tb, **kw)
+    tb = tv.copy()
+    tb[7, 1] = np.inf  # a weight must be finite
+    with pytest.raises(jag.JagError):
+        jag.jag_build_graph(X, thr_values=tb, **kw)
+    with pytest.raises(ValueError):
+        jag.jag_build_graph(X, thr_values=tv[:10], **kw)

@@ -1,0 +1,97 @@
+"""GPU graph construction (Algorithms 3 and 4 with the App. D.3 notes;
+Section 3.4 for weight entries) against the oracle and the host builder.
+
+* Rounds of one point with the oracle's insertion order and thresholds: the
+  device builder performs the oracle's sequential construction, so the graphs
+  agree edge for edge.
+* Default rounds: the device builder forms every value in the host builder's
+  order (canonical FP32 distance, one fused multiply-add per weight entry),
+  so it gives the host builder's graph edge for edge, for every comparator
+  kind, odd and large dimensions included."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2602_10258_amd import jag
+from workloads import make_config
+
+from .test_build_parity import CASES, oracle_graph, small_world
+
+pytestmark = pytest.mark.gpu
+
+W = jag.THRESHOLD_WEIGHT
+S, LB, LW = jag.ATTR_SCALAR, jag.ATTR_LABELS, jag.ATTR_LABELS_WEIGHTED
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("case", ["scalar", "labels", "mixed5", "weight"])
+def test_device_rounds_of_one_give_the_oracle_graph(case):
+    n, d, R, lb, thr = CASES[case]
+    X, scal, loff, lab = small_world(n, d, seed=len(case))
+    oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, R, lb, thr, seed=3)
+    _say("device build, rounds of one:", case, n, d, R)
+    adj, entry = jag.jag_build_graph(X, scalar=scal, label_off=loff, labels=lab, vocab=12, R=R, L_build=lb,
+                                     thresholds=thr, max_batch=1, order=order, thr_values=tv, device=True)
+    assert entry == oentry
+    assert np.array_equal(adj, oadj), f"{np.sum(np.any(adj != oadj, axis=1))} rows differ"
+
+
+def _world(name):
+    if name == "c1":
+        w = make_config("c1")
+        return w, dict(label_off=w.loff, labels=w.lab, vocab=w.vocab), 32, [(LB, 1.0), (LB, 0.0)]
+    if name == "c2":
+        w = make_config("c2", n=20000, nq=10)
+        return w, dict(scalar=w.scalar), 64, [(S, 1.0), (S, 0.01), (S, 0.0)]
+    if name == "c2w":
+        w = make_config("c2", n=20000, nq=10)
+        return w, dict(scalar=w.scalar), 48, [(S | W, 0.0), (S | W, 10.0), (S | W, 1000.0)]
+    if name == "c3":
+        w = make_config("c3", n=20000, nq=10)
+        return w, dict(label_off=w.loff, labels=w.lab, vocab=w.vocab), 32, [(LW, 1.0), (LW, 0.01), (LW, 0.0)]
+    if name == "c5":
+        w = make_config("c5", n=20000, nq=10)
+        return (w, dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab), 40,
+                [(S, 1.0), (S, 0.01), (S, 0.0), (LW, 0.01), (LB, 0.0)])
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c2w", "c3", "c5"])
+def test_device_build_equals_host_build(name):
+    w, attrs, R, thr = _world(name)
+    kw = dict(R=R, thresholds=thr, seed=11, **attrs)
+    _say("host build", name, w.X.shape, R, thr)
+    hadj, hentry = jag.jag_build_graph(w.X, **kw)
+    _say("device build", name)
+    dadj, dentry = jag.jag_build_graph(w.X, device=True, **kw)
+    assert dentry == hentry
+    diff = np.sum(np.any(dadj != hadj, axis=1))
+    _say("rows differing", diff, "mean degree", float(np.mean(np.sum(dadj >= 0, axis=1))))
+    assert diff == 0
+
+
+@pytest.mark.parametrize("d", [37, 200])
+def test_device_build_odd_and_large_dimensions(d):
+    X, scal, loff, lab = small_world(3000, d, seed=d)
+    kw = dict(scalar=scal, label_off=loff, labels=lab, vocab=12, R=24,
+              thresholds=[(S, 1.0), (LB, 0.0), (S | W, 5.0)], seed=2)
+    hadj, he = jag.jag_build_graph(X, **kw)
+    _say("device build d =", d)
+    dadj, de = jag.jag_build_graph(X, device=True, **kw)
+    assert de == he and np.array_equal(dadj, hadj)
+
+
+def test_device_build_index_and_limits():
+    X, scal, loff, lab = small_world(500, 16, seed=9)
+    with pytest.raises(jag.JagError):  # the device beam holds at most 256
+        jag.jag_build_graph(X, scalar=scal, R=16, L_build=300, thresholds=[(S, 1.0)], device=True)
+    _say("jag_build on the device")
+    idx = jag.jag_build(X, scalar=scal, R=16, thresholds=[(S, 1.0), (S, 0.0)], device=True, seed=4)
+    hadj, he = jag.jag_build_graph(X, scalar=scal, R=16, thresholds=[(S, 1.0), (S, 0.0)], seed=4)
+    adj, e = jag.jag_get_graph(idx)
+    assert e == he and np.array_equal(adj, hadj)
