@@ -68,9 +68,30 @@ def parse():
                          "workloads c3 and c5, else 0)")
     ap.add_argument("--filter-type", type=int, default=None, choices=[0, 1, 2, 3, 4],
                     help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
+    ap.add_argument("--build", default="device", choices=["device", "host", "both"],
+                    help="where the graph is built (both: host and device, checked equal, both timed)")
     ap.add_argument("--graph-cache", default=None,
                     help="load the graph from this .npz if present, else build and save it there")
     return ap.parse_args()
+
+
+def build_graph(args, w, thresholds):
+    """The workload's graph on the GPU and/or host threads (the same graph);
+    returns (adj, entry, {where: seconds})."""
+    kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab, R=w.R, L_build=2 * w.R,
+              thresholds=thresholds, seed=0, progress=True)
+    times, out = {}, {}
+    for where in (["host", "device"] if args.build == "both" else [args.build]):
+        t = time.time()
+        out[where] = jag.jag_build_graph(w.X, device=where == "device", **kw)
+        times[where] = round(time.time() - t, 2)
+        log(f"graph built on the {where} in {times[where]:.2f}s")
+    if len(out) == 2:
+        same = out["host"][1] == out["device"][1] and np.array_equal(out["host"][0], out["device"][0])
+        log(f"host and device graphs identical: {same}")
+        assert same, "the device builder must give the host builder's graph"
+    adj, entry = out["device" if "device" in out else "host"]
+    return adj, entry, times
 
 
 class Timer:
@@ -165,9 +186,7 @@ def serve_main(args):
         z = np.load(args.graph_cache)
         adj, entry = z["adj"], int(z["entry"])
     else:
-        adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
-                                         vocab=w.vocab, R=w.R, L_build=2 * w.R,
-                                         thresholds=THRESHOLDS["c5"], seed=0, progress=True)
+        adj, entry, _ = build_graph(args, w, THRESHOLDS["c5"])
         if args.graph_cache:
             np.savez(args.graph_cache, adj=adj, entry=entry)
     log(f"graph ready in {time.time() - t1:.1f}s")
@@ -290,11 +309,10 @@ def main():
     if args.graph_cache and os.path.exists(args.graph_cache):
         z = np.load(args.graph_cache)
         adj, entry = z["adj"], int(z["entry"])
+        build_times = {"cached": 0.0}
         log(f"graph loaded from {args.graph_cache}")
     else:
-        adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab,
-                                         vocab=w.vocab, R=w.R, L_build=2 * w.R,
-                                         thresholds=THRESHOLDS[w.name], seed=0, progress=True)
+        adj, entry, build_times = build_graph(args, w, THRESHOLDS[w.name])
         if args.graph_cache:
             np.savez(args.graph_cache, adj=adj, entry=entry)
     build_s = time.time() - t1
@@ -572,6 +590,7 @@ def main():
         "mean_expansions": round(float(st[:, 0].mean()), 2),
         "mean_distance_computations": round(float(st[:, 1].mean()), 2),
         "build_seconds": round(build_s, 1),
+        "graph_build_seconds": build_times,
         "sweeps": {"fixed": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
                              for r in fixed],
                    "bf16_rerank_fixed": [{k_: (round(v, 4) if isinstance(v, float) else v)

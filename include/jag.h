@@ -202,19 +202,29 @@ typedef struct {
  * alpha test, and each bucket stops at ceil(0.9 R / |T|)).  Points are
  * inserted in parallel rounds of growing size; within a round every
  * insertion searches the graph as it stood before the round, so the result
- * depends only on the seed, not on the thread count.  The graph, attributes
- * and vector store are then placed in device memory of the current device.
- * Errors: EINVAL (n < 1, d < 1, d > 512, bad params or attributes),
- * ENOMEM, EDEVICE.
+ * depends only on the seed (or the given order and thresholds), not on the
+ * thread count.  Each insertion search stops after 4 l_b expansions.  The
+ * rounds run on host threads (P->device = 0) or on the current GPU
+ * (P->device = 1); both form every distance in one fixed FP32 order and give
+ * the same graph.  With max_batch = 1 every round holds one point: the
+ * sequential construction of Algorithm 3.  The graph, attributes and vector
+ * store are then placed in device memory of the current device.
+ * Errors: EINVAL (n < 1, d < 1, d > 512, bad params, attributes, order or
+ * thresholds; L_build > 256 on the device), ENOMEM, EDEVICE, EUNSUPPORTED
+ * (device rounds only: one insertion expanding more than 4096 vertices over
+ * all its searches, or a vertex gaining more than 4096 - R in-links in one
+ * round; a smaller max_batch avoids the latter).
  */
 jag_status jag_build(const float *X, int64_t n, int32_t d, const jag_attrs *A,
                      const jag_build_params *P, jag_index **out);
 
 /*
- * The graph construction of jag_build alone, on host threads, with no
- * device involved: writes adj_out[n][P->R] (host, -1 padded) and the entry
- * vertex to *entry.  P->store and P->keep_f32 are ignored.  Same errors as
- * jag_build except EDEVICE.
+ * The graph construction of jag_build alone: writes adj_out[n][P->R] (host,
+ * -1 padded) and the entry vertex to *entry.  With P->device = 0 no device
+ * is involved; with P->device = 1 the rounds run on the current GPU, which
+ * holds the FP32 vectors (padded to a multiple of 4 floats), the attributes
+ * and the graph while it builds.  P->store and P->keep_f32 are ignored.
+ * Same errors as jag_build.
  */
 jag_status jag_build_graph(const float *X, int64_t n, int32_t d, const jag_attrs *A,
                            const jag_build_params *P, int32_t *adj_out, int32_t *entry);
