@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--ntrain", type=int, default=20000)
     ap.add_argument("--cpu-sample", type=int, default=10000)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="repeat the CPU baseline over its sample for about this long")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-fixed", action="store_true")
     ap.add_argument("--profile-op", action="store_true",
@@ -70,6 +72,8 @@ def parse():
                     help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--build", default="device", choices=["device", "host", "both"],
                     help="where the graph is built (both: host and device, checked equal, both timed)")
+    ap.add_argument("--build-only", action="store_true",
+                    help="build the workload's graph (see --build), print the build times, exit")
     ap.add_argument("--graph-cache", default=None,
                     help="load the graph from this .npz if present, else build and save it there")
     return ap.parse_args()
@@ -78,6 +82,7 @@ def parse():
 def build_graph(args, w, thresholds):
     """The workload's graph on the GPU and/or host threads (the same graph);
     returns (adj, entry, {where: seconds})."""
+    from paper_2602_10258_amd import jag
     kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab, R=w.R, L_build=2 * w.R,
               thresholds=thresholds, seed=0, progress=True)
     times, out = {}, {}
@@ -304,7 +309,7 @@ def main():
     k = w.k
     log(f"workload {w.name}: n={w.n} d={w.d} nq={w.nq} ({time.time() - t0:.1f}s)")
 
-    # ---- build (host threads) and lay out the two stores over one graph
+    # ---- build the graph and lay out the two stores over it
     t1 = time.time()
     if args.graph_cache and os.path.exists(args.graph_cache):
         z = np.load(args.graph_cache)
@@ -317,6 +322,12 @@ def main():
             np.savez(args.graph_cache, adj=adj, entry=entry)
     build_s = time.time() - t1
     log(f"graph built in {build_s:.1f}s, mean degree {(adj >= 0).sum(1).mean():.1f}")
+    if args.build_only:
+        print(json.dumps({"workload": w.name, "n": w.n, "d": w.d, "R": w.R, "L_build": 2 * w.R,
+                          "thresholds": [list(t) for t in THRESHOLDS[w.name]],
+                          "graph_build_seconds": build_times,
+                          "mean_degree": round(float((adj >= 0).sum(1).mean()), 2)}))
+        return
     kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
     ix32 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_F32, **kw)
     ix16 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_BF16, keep_f32=True, **kw)
@@ -548,11 +559,14 @@ def main():
     if not args.no_cpu:
         m = min(args.cpu_sample, nq)
         Lcpu = op["point"].get("L", best_f["L"] if best_f else 64)
-        t4 = time.time()
-        O.search(w.X, adj, entry, A, w.Q[:m], w.F[:m], w.pool, Lcpu, k, nthreads=nthr)
-        cs = time.time() - t4
-        cpu = {"value": m / cs, "unit": "queries/s", "cores": nthr, "kind": "oracle",
-               "sample": f"first {m} of the {nq} queries, plain FP32 fixed beam L={Lcpu}, "
+        reps, cs = 0, 0.0
+        while reps == 0 or cs < args.cpu_seconds:  # whole passes over the sample, about cpu_seconds
+            t4 = time.time()
+            O.search(w.X, adj, entry, A, w.Q[:m], w.F[:m], w.pool, Lcpu, k, nthreads=nthr)
+            cs += time.time() - t4
+            reps += 1
+        cpu = {"value": reps * m / cs, "unit": "queries/s", "cores": nthr, "kind": "oracle",
+               "sample": f"first {m} of the {nq} queries, {reps} passes, plain FP32 fixed beam L={Lcpu}, "
                          f"FP64 distances, {cs:.1f}s"}
 
     out = {

@@ -715,9 +715,15 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
     int32_t *dorder, *dadj, *dexp, *dexpcnt, *dincnt, *dfill, *dseg, *dtouch, *dinl, *dctr;
     unsigned long long *dptot;
     HIP_OK(B.alloc(&dX, (size_t)n * d4));
-    HIP_OK(hipMemset(dX, 0, (size_t)n * d4 * sizeof(float)));
-    HIP_OK(hipMemcpy2D(dX, (size_t)d4 * sizeof(float), X, (size_t)d * sizeof(float), (size_t)d * sizeof(float),
-                       (size_t)n, hipMemcpyHostToDevice));
+    if (d4 == d) {
+        HIP_OK(hipMemcpy(dX, X, (size_t)n * d * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        // one contiguous copy of rows padded on the host (a pitched copy from
+        // pageable memory goes row by row)
+        std::vector<float> pad((size_t)n * d4, 0.f);
+        for (int64_t i = 0; i < n; i++) std::copy(X + i * d, X + (i + 1) * d, pad.begin() + i * d4);
+        HIP_OK(hipMemcpy(dX, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     if (A.scalar) {
         HIP_OK(B.alloc(&dscal, (size_t)n));
         HIP_OK(hipMemcpy(dscal, A.scalar, (size_t)n * 4, hipMemcpyHostToDevice));
