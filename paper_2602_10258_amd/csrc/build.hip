@@ -370,10 +370,11 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
     }
 }
 
-// Bytes of LDS one prune wave uses for P candidate slots.
-__host__ __device__ constexpr int prune_wave_bytes(int P)
+// Bytes of LDS one prune wave uses for P candidate slots and memf floats of
+// member rows.
+__host__ __device__ constexpr int prune_wave_bytes(int P, int memf)
 {
-    return P * (4 + 4 + 4 + 2 + 1) + kMaxOut * 4 + 16;
+    return memf * 4 + P * (4 + 4 + 4 + 2 + 1) + kMaxOut * 4 + 64 * 4 + 16;
 }
 
 // Ascending bitonic sort of ids in LDS (P a power of two, padded with INT_MAX).
@@ -418,34 +419,63 @@ __device__ int unique_ids(int32_t *x, int P, int lane)
     return out;
 }
 
+// Squared distance between the candidate row a group of eight lanes holds
+// in registers (lane g: elements 32c + 4g .. +3) and a row at m, folded in the
+// canonical order (as dist8x4).
+template <int CH>
+__device__ __forceinline__ float dist_reg(const float4 (&r)[CH], const float *__restrict m, int d4, int g)
+{
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+    for (int c = 0; c < CH; c++) {
+        const int e = 32 * c + 4 * g;
+        if (e < d4) {
+            const float4 u = *reinterpret_cast<const float4 *>(m + e);
+            const float t0 = u.x - r[c].x, t1 = u.y - r[c].y, t2 = u.z - r[c].z, t3 = u.w - r[c].w;
+            a0 = __builtin_fmaf(t0, t0, a0);
+            a1 = __builtin_fmaf(t1, t1, a1);
+            a2 = __builtin_fmaf(t2, t2, a2);
+            a3 = __builtin_fmaf(t3, t3, a3);
+        }
+    }
+    float s = (a0 + a1) + (a2 + a3);
+    s = s + __shfl_xor(s, 4);
+    s = s + __shfl_xor(s, 2);
+    s = s + __shfl_xor(s, 1);
+    return s;
+}
+
 // JointRobustPrune(G, v, V, R, alpha, T) with the App. D.3 notes over the
 // sorted distinct ids V[0..nv): per comparator entry, candidates in order of
 // (first component, squared distance, id); one chosen by an earlier entry
 // joins without the alpha test; the others join when alpha^2 d^2(u, c) >
 // d^2(v, c) for every member u already in the bucket; the bucket closes at
-// cap members.  Each accepted member removes the candidates it rules out
-// from the rest of the ordered list at once, which decides every candidate
-// exactly as testing it against the bucket when its turn comes.  Writes the
+// cap members.  The ordered list is walked in chunks of 8U candidates whose
+// rows are loaded once into registers (group g of eight lanes holds the
+// candidates at chunk positions 8k + g); each is tested against the members
+// accepted before the chunk, then the chunk is decided in list order, every
+// member it accepts being tested against the candidates after it.  Member rows
+// sit in LDS (mem) when they fit, else they are read from X.  Writes the
 // first R chosen ids into v's row.
+template <int CH, int U>
 __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float *pd2, float *fst,
-                           uint16_t *ord, uint8_t *flg, int32_t *outl, int P, int lane)
+                           uint16_t *ord, uint8_t *flg, int32_t *outl, int32_t *mid, float *mem, int lane)
 {
+    const int g = lane & 7, grp = lane >> 3;
     const float *xv = a.X + v * a.d4;
     for (int c0 = 0; c0 < nv; c0 += 32) {
         const float *xb[4];
-        bool act[4];
         int cc[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            cc[k] = c0 + k * 8 + (lane >> 3);
-            act[k] = cc[k] < nv;
-            xb[k] = a.X + (int64_t)(act[k] ? V[cc[k]] : 0) * a.d4;
+            cc[k] = c0 + k * 8 + grp;
+            xb[k] = a.X + (int64_t)(cc[k] < nv ? V[cc[k]] : 0) * a.d4;
         }
         float d2[4];
-        dist8x4(xv, xb, a.d4, lane & 7, d2);
+        dist8x4(xv, xb, a.d4, g, d2);
 #pragma unroll
         for (int k = 0; k < 4; k++)
-            if (act[k] && (lane & 7) == 0) pd2[cc[k]] = d2[k];
+            if (cc[k] < nv && g == 0) pd2[cc[k]] = d2[k];
     }
     for (int j = lane; j < nv; j += 64) flg[j] = 0;
     wave_sync();
@@ -484,52 +514,77 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
                 }
                 wave_sync();
             }
-        // the ordered list ord[0..na) holds the candidates still open
-        int na = nv, bucket = 0;
-        while (na > 0) {
-            const int o = ord[0];
-            bucket++;
-            if (!(flg[o] & 1)) {
-                if (lane == 0) {
-                    flg[o] = 1;
-                    if (nout < kMaxOut) outl[nout] = V[o];
-                }
-                nout++;
-            }
-            wave_sync();
-            if (bucket >= a.cap) break;
-            const float *xo = a.X + (int64_t)V[o] * a.d4;
-            // test ord[1..na) against the new member, keeping the order
-            int w = 0;
-            for (int c0 = 1; c0 < na; c0 += 32) {
-                const float *xb[4];
-                bool act[4], in[4];
-                int oc[4];
+        int nm = 0;  // members of this bucket
+        for (int c0 = 0; c0 < nv && nm < a.cap; c0 += 8 * U) {
+            float4 row[U][CH];
+            int oc[U];
+            bool in[U], fl[U], alive[U];
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int q = c0 + k * 8 + (lane >> 3);
-                    in[k] = q < na;
-                    oc[k] = in[k] ? ord[q] : 0;
-                    act[k] = in[k] && !(flg[oc[k]] & 1);  // chosen earlier: joins without the test
-                    xb[k] = a.X + (int64_t)(act[k] ? V[oc[k]] : 0) * a.d4;
-                }
-                float d2[4];
-                dist8x4(xo, xb, a.d4, lane & 7, d2);
-                wave_sync();
+            for (int k = 0; k < U; k++) {
+                const int q = c0 + 8 * k + grp;
+                in[k] = q < nv;
+                oc[k] = in[k] ? ord[q] : 0;
+                fl[k] = in[k] && (flg[oc[k]] & 1);
+                alive[k] = in[k];
+                const float *src = a.X + (int64_t)(in[k] ? V[oc[k]] : 0) * a.d4;
 #pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const bool keep = in[k] && (!act[k] || a.alpha2 * d2[k] > pd2[oc[k]]);
-                    const uint64_t mk = __ballot(keep && (lane & 7) == 0);
-                    // group leaders in lane order are the candidates in list order
-                    const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-                    if (keep && (lane & 7) == 0) ord[w + r] = (uint16_t)oc[k];
-                    w += __popcll(mk);
+                for (int c = 0; c < CH; c++) {
+                    const int e = 32 * c + 4 * g;
+                    row[k][c] = e < a.d4 ? *reinterpret_cast<const float4 *>(src + e) : float4{0.f, 0.f, 0.f, 0.f};
                 }
-                wave_sync();
             }
-            na = w;
+            // the members accepted before this chunk
+            for (int j = 0; j < nm; j++) {
+                bool any = false;
+#pragma unroll
+                for (int k = 0; k < U; k++) any = any || (alive[k] && !fl[k]);
+                if (!__ballot(any)) break;
+                const float *mrow = mem ? mem + (size_t)j * a.d4 : a.X + (int64_t)mid[j] * a.d4;
+#pragma unroll
+                for (int k = 0; k < U; k++) {
+                    const float d2 = dist_reg<CH>(row[k], mrow, a.d4, g);
+                    if (alive[k] && !fl[k] && !(a.alpha2 * d2 > pd2[oc[k]])) alive[k] = false;
+                }
+            }
+            // decide the chunk in list order
+#pragma unroll
+            for (int k = 0; k < U; k++) {
+                for (int gg = 0; gg < 8; gg++) {
+                    const bool take = __shfl((int)(alive[k] || fl[k]), 8 * gg) != 0;
+                    if (!take) continue;
+                    const int o = __shfl(oc[k], 8 * gg);
+                    if (!(flg[o] & 1)) {
+                        if (lane == 0) {
+                            flg[o] = 1;
+                            if (nout < kMaxOut) outl[nout] = V[o];
+                        }
+                        nout++;
+                    }
+                    if (lane == 0) mid[nm] = V[o];
+                    if (mem && grp == gg) {
+#pragma unroll
+                        for (int c = 0; c < CH; c++) {
+                            const int e = 32 * c + 4 * g;
+                            if (e < a.d4) *reinterpret_cast<float4 *>(mem + (size_t)nm * a.d4 + e) = row[k][c];
+                        }
+                    }
+                    nm++;
+                    wave_sync();
+                    if (nm >= a.cap) break;
+                    // the candidates after it in this chunk meet the new member
+                    const float *mrow = mem ? mem + (size_t)(nm - 1) * a.d4 : a.X + (int64_t)V[o] * a.d4;
+#pragma unroll
+                    for (int k2 = 0; k2 < U; k2++) {
+                        if (k2 < k) continue;
+                        const float d2 = dist_reg<CH>(row[k2], mrow, a.d4, g);
+                        const bool later = k2 > k || grp > gg;
+                        if (later && alive[k2] && !fl[k2] && !(a.alpha2 * d2 > pd2[oc[k2]])) alive[k2] = false;
+                    }
+                }
+                if (nm >= a.cap) break;
+            }
         }
+        wave_sync();
     }
     const int m = min(nout, a.R);
     int32_t *row = a.adj + v * a.R;
@@ -538,15 +593,19 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
 
 // Mode 0: prune the union of a new point's expanded sets into its row.
 // Mode 1: merge a target's new in-links into its row (re-pruned above R).
-__global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, int32_t mode, int32_t P)
+template <int CH, int U>
+__global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, int32_t mode, int32_t P,
+                                                         int32_t memf)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
-    int32_t *V = reinterpret_cast<int32_t *>(smem);
+    float *mem = memf > 0 ? reinterpret_cast<float *>(smem) : nullptr;
+    int32_t *V = reinterpret_cast<int32_t *>(smem + (size_t)memf * 4);
     float *pd2 = reinterpret_cast<float *>(V + P);
     float *fst = pd2 + P;
     int32_t *outl = reinterpret_cast<int32_t *>(fst + P);
-    uint16_t *ord = reinterpret_cast<uint16_t *>(outl + kMaxOut);
+    int32_t *mid = outl + kMaxOut;
+    uint16_t *ord = reinterpret_cast<uint16_t *>(mid + 64);
     uint8_t *flg = reinterpret_cast<uint8_t *>(ord + P);
 
     if (mode == 0) {
@@ -565,7 +624,7 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
         wave_sync();
         sort_ids(V, P2, lane);
         const int nv = unique_ids(V, P2, lane);
-        prune_core(a, p, V, nv, pd2, fst, ord, flg, outl, P, lane);
+        prune_core<CH, U>(a, p, V, nv, pd2, fst, ord, flg, outl, mid, mem, lane);
         return;
     }
     const int64_t v = a.touched[blockIdx.x];
@@ -609,7 +668,7 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
         wave_sync();
         sort_ids(V, P3, lane);
         const int nv = unique_ids(V, P3, lane);
-        prune_core(a, v, V, nv, pd2, fst, ord, flg, outl, P, lane);
+        prune_core<CH, U>(a, v, V, nv, pd2, fst, ord, flg, outl, mid, mem, lane);
     }
     if (lane == 0) {
         a.incnt[v] = 0;
@@ -677,6 +736,21 @@ struct DevBufs {
         return e;
     }
 };
+
+// Member rows go to LDS when the wave's LDS stays within 64 KB.
+hipError_t launch_prune(const BArgs &a, int32_t grid, int64_t pos, int32_t mode, int32_t P)
+{
+    const int memf = prune_wave_bytes(P, a.cap * a.d4) <= 65536 ? a.cap * a.d4 : 0;
+    const size_t lds = (size_t)prune_wave_bytes(P, memf);
+    const dim3 gr((unsigned)grid), bl(64);
+    // a candidate row takes ceil(d4 / 32) float4 per lane; four candidates per
+    // group of eight lanes up to d4 = 128, one above
+    if (a.d4 <= 64) hipLaunchKernelGGL((build_prune_kernel<2, 4>), gr, bl, lds, 0, a, pos, mode, P, memf);
+    else if (a.d4 <= 96) hipLaunchKernelGGL((build_prune_kernel<3, 4>), gr, bl, lds, 0, a, pos, mode, P, memf);
+    else if (a.d4 <= 128) hipLaunchKernelGGL((build_prune_kernel<4, 4>), gr, bl, lds, 0, a, pos, mode, P, memf);
+    else hipLaunchKernelGGL((build_prune_kernel<16, 1>), gr, bl, lds, 0, a, pos, mode, P, memf);
+    return hipGetLastError();
+}
 
 int pow2_at_least(int x)
 {
@@ -804,9 +878,7 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
             return JAG_EUNSUPPORTED;
         }
         const int P1 = pow2_at_least(hctr[3]);
-        hipLaunchKernelGGL(build_prune_kernel, dim3((unsigned)nb), dim3(64), prune_wave_bytes(P1), 0, a, pos, 0,
-                           P1);
-        HIP_OK(hipGetLastError());
+        HIP_OK(launch_prune(a, nb, pos, 0, P1));
         const unsigned eb = (unsigned)(((int64_t)nb * R + 255) / 256);
         hipLaunchKernelGGL(rev_count_kernel, dim3(eb), dim3(256), 0, 0, a, pos, nb);
         HIP_OK(hipGetLastError());
@@ -822,9 +894,7 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
                 return JAG_EUNSUPPORTED;
             }
             const int P2 = pow2_at_least(hctr[2] + R);
-            hipLaunchKernelGGL(build_prune_kernel, dim3((unsigned)hctr[0]), dim3(64), prune_wave_bytes(P2), 0, a,
-                               pos, 1, P2);
-            HIP_OK(hipGetLastError());
+            HIP_OK(launch_prune(a, hctr[0], pos, 1, P2));
         }
         if (cfg.progress && (pos * 10) / n != (be * 10) / n) {
             HIP_OK(hipDeviceSynchronize());
