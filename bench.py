@@ -72,6 +72,9 @@ def parse():
                     help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--build", default="device", choices=["device", "host", "both"],
                     help="where the graph is built (both: host and device, checked equal, both timed)")
+    ap.add_argument("--thresholds", default=None,
+                    help="comparator list of the build, e.g. 'labels:1,labels:0.01,labels:0' or "
+                         "'weight:labels:0,weight:labels:1,weight:labels:10' (default: the workload's)")
     ap.add_argument("--build-only", action="store_true",
                     help="build the workload's graph (see --build), print the build times, exit")
     ap.add_argument("--graph-cache", default=None,
@@ -152,6 +155,24 @@ THRESHOLDS = {
     # 15 binary variables as labels: |a XOR b| is the Hamming distance of assignments
     "bool15": [(1, 1.0), (1, 0.01), (1, 0.0)],
 }
+
+
+KIND_NAMES = {"scalar": 0, "labels": 1, "wlabels": 2}
+
+
+def parse_thresholds(text: str):
+    """'labels:1,labels:0.01,labels:0' -> [(1, 1.0), (1, 0.01), (1, 0.0)];
+    a 'weight:' prefix makes a Weight-JAG entry (value = the multiplier)."""
+    out = []
+    for item in text.split(","):
+        parts = item.strip().split(":")
+        weight = parts[0] == "weight"
+        if weight:
+            parts = parts[1:]
+        if len(parts) != 2 or parts[0] not in KIND_NAMES:
+            raise SystemExit(f"bad threshold entry {item!r}: want [weight:]scalar|labels|wlabels:value")
+        out.append((KIND_NAMES[parts[0]] | (0x100 if weight else 0), float(parts[1])))
+    return out
 
 
 def measured_traffic(workload: str, op_name: str):
@@ -310,6 +331,7 @@ def main():
     log(f"workload {w.name}: n={w.n} d={w.d} nq={w.nq} ({time.time() - t0:.1f}s)")
 
     # ---- build the graph and lay out the two stores over it
+    thr_list = parse_thresholds(args.thresholds) if args.thresholds else THRESHOLDS[w.name]
     t1 = time.time()
     if args.graph_cache and os.path.exists(args.graph_cache):
         z = np.load(args.graph_cache)
@@ -317,14 +339,14 @@ def main():
         build_times = {"cached": 0.0}
         log(f"graph loaded from {args.graph_cache}")
     else:
-        adj, entry, build_times = build_graph(args, w, THRESHOLDS[w.name])
+        adj, entry, build_times = build_graph(args, w, thr_list)
         if args.graph_cache:
             np.savez(args.graph_cache, adj=adj, entry=entry)
     build_s = time.time() - t1
     log(f"graph built in {build_s:.1f}s, mean degree {(adj >= 0).sum(1).mean():.1f}")
     if args.build_only:
         print(json.dumps({"workload": w.name, "n": w.n, "d": w.d, "R": w.R, "L_build": 2 * w.R,
-                          "thresholds": [list(t) for t in THRESHOLDS[w.name]],
+                          "thresholds": [list(t) for t in thr_list],
                           "graph_build_seconds": build_times,
                           "mean_degree": round(float((adj >= 0).sum(1).mean()), 2)}))
         return
@@ -575,7 +597,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n} x {w.d} clustered vectors, {nq} queries "
-                               f"({w.meta.get('thresholds')}), k={k}, R={w.R}",
+                               f"({args.thresholds or w.meta.get('thresholds')}), k={k}, R={w.R}",
                    "global_batch": nq, "mode": op["mode"], "recall_at_10": round(rec_final, 4),
                    "filter_types": sorted({FILTER_NAMES[int(t)] for t in w.F[:, 0]}),
                    "storage": {jag.STORE_F32: "fp32", jag.STORE_BF16: "bf16 (+fp32 rerank)",
