@@ -160,6 +160,17 @@ THRESHOLDS = {
 KIND_NAMES = {"scalar": 0, "labels": 1, "wlabels": 2}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def parse_thresholds(text: str):
     """'labels:1,labels:0.01,labels:0' -> [(1, 1.0), (1, 0.01), (1, 0.0)];
     a 'weight:' prefix makes a Weight-JAG entry (value = the multiplier)."""
@@ -577,7 +588,7 @@ def main():
     traffic = measured_traffic(w.name, op_name)
 
     # ---- CPU baseline: the oracle, unchanged, on a bounded sample at the same beam
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         m = min(args.cpu_sample, nq)
         Lcpu = op["point"].get("L", best_f["L"] if best_f else 64)
@@ -590,6 +601,12 @@ def main():
         cpu = {"value": reps * m / cs, "unit": "queries/s", "cores": nthr, "kind": "oracle",
                "sample": f"first {m} of the {nq} queries, {reps} passes, plain FP32 fixed beam L={Lcpu}, "
                          f"FP64 distances, {cs:.1f}s"}
+        # the same on one thread, over a tenth of the sample
+        m1 = max(1, m // 10)
+        t4 = time.time()
+        O.search(w.X, adj, entry, A, w.Q[:m1], w.F[:m1], w.pool, Lcpu, k, nthreads=1)
+        cpu1 = {"value": round(m1 / (time.time() - t4), 1), "unit": "queries/s", "cores": 1,
+                "sample": f"first {m1} queries, same beam", "cpu_model": cpu_model()}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
@@ -607,6 +624,7 @@ def main():
         "operating_point": op_name,
         "learned_ladder": None if lad is None else lad.tolist(),
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
         "qps_at_095": {
             "learned_bf16_measured": best_l and round(best_l["qps"], 1),
             "learned_bf16_interp": interp_l and round(interp_l, 1),

@@ -203,7 +203,7 @@ typedef struct {
  * inserted in parallel rounds of growing size; within a round every
  * insertion searches the graph as it stood before the round, so the result
  * depends only on the seed (or the given order and thresholds), not on the
- * thread count.  Each insertion search stops after 4 l_b expansions.  The
+ * thread count.  Each insertion search stops after 4 l_b + 64 expansions.  The
  * rounds run on host threads (P->device = 0) or on the current GPU
  * (P->device = 1); both form every distance in one fixed FP32 order and give
  * the same graph.  With max_batch = 1 every round holds one point: the

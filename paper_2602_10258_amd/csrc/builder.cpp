@@ -182,7 +182,7 @@ struct Scratch {
 // GreedySearch(G, x_p, 1, l_b, D_A^t) over the frozen graph; appends the
 // expanded vertices to s.visited.  A vertex seen earlier in this search is
 // not re-evaluated: the beam always holds the l_b best vertices discovered,
-// so one that fell out can never get back in.  At most hopcap = 4 l_b
+// so one that fell out can never get back in.  At most hopcap = 4 l_b + 64
 // expansions (a bound the searches stay far below; it sizes the device
 // builder's candidate buffers).
 void greedy_build_search(const Builder &B, Scratch &s, int64_t p, int ti)
@@ -300,7 +300,7 @@ int plan_build(const float *X, int64_t n, int32_t d, const AttrView &A, const Bu
     P.lb = cfg.L_build > 0 ? cfg.L_build : 2 * cfg.R;
     P.nT = (int)cfg.kinds.size();
     P.cap = (9 * P.R + 10 * P.nT - 1) / (10 * P.nT);
-    P.hopcap = 4 * P.lb;
+    P.hopcap = 4 * P.lb + 64;
     P.alpha2 = cfg.alpha * cfg.alpha;
     P.kinds = cfg.kinds;
     P.max_batch = cfg.max_batch > 0 ? cfg.max_batch : std::max<int64_t>(64, n / 50);

@@ -81,3 +81,39 @@ def test_given_order_and_thresholds_are_checked():
         jag.jag_build_graph(X, thr_values=tb, **kw)
     with pytest.raises(ValueError):
         jag.jag_build_graph(X, thr_values=tv[:10], **kw)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17])
+def test_tiny_worlds_match_the_oracle(n):
+    X, scal, loff, lab = small_world(n, 4, seed=n)
+    thr = [(S, 1.0), (S, 0.0)]
+    oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, 4, 8, thr, seed=1)
+    adj, entry = jag.jag_build_graph(X, scalar=scal, R=4, L_build=8, thresholds=thr, max_batch=1,
+                                     order=order, thr_values=tv, n_threads=2)
+    assert entry == oentry and np.array_equal(adj, oadj)
+
+
+def test_duplicate_vectors_and_equal_attributes_match_the_oracle():
+    """Ties in both components fall to the id in both builders."""
+    rng = np.random.default_rng(4)
+    base = rng.normal(size=(40, 8)).astype(np.float32)
+    X = np.repeat(base, 5, axis=0)                      # every vector five times
+    scal = np.repeat(rng.integers(0, 4, size=40), 5).astype(np.int32)
+    loff = np.arange(X.shape[0] + 1, dtype=np.int64)
+    lab = np.zeros(X.shape[0], np.int32)
+    thr = [(S, 1.0), (S, 0.0), (LB, 0.0)]
+    oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, 8, 16, thr, seed=2)
+    adj, entry = jag.jag_build_graph(X, scalar=scal, label_off=loff, labels=lab, vocab=1, R=8, L_build=16,
+                                     thresholds=thr, max_batch=1, order=order, thr_values=tv, n_threads=2)
+    assert entry == oentry and np.array_equal(adj, oadj)
+
+
+def test_degree_one_beam_one_and_eight_entries_match_the_oracle():
+    X, scal, loff, lab = small_world(300, 12, seed=8)
+    for R, lb, thr in [(1, 1, [(S, 1.0)]), (6, 1, [(S, 1.0), (S, 0.0)]),
+                       (16, 20, [(S, 1.0), (S, 0.5), (S, 0.2), (S, 0.05), (S, 0.0), (LB, 1.0), (LB, 0.0),
+                                 (S | W, 3.0)])]:
+        oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, R, lb, thr, seed=5)
+        adj, entry = jag.jag_build_graph(X, scalar=scal, label_off=loff, labels=lab, vocab=12, R=R, L_build=lb,
+                                         thresholds=thr, max_batch=1, order=order, thr_values=tv, n_threads=2)
+        assert entry == oentry and np.array_equal(adj, oadj), (R, lb, len(thr))

@@ -95,3 +95,59 @@ def test_device_build_index_and_limits():
     hadj, he = jag.jag_build_graph(X, scalar=scal, R=16, thresholds=[(S, 1.0), (S, 0.0)], seed=4)
     adj, e = jag.jag_get_graph(idx)
     assert e == he and np.array_equal(adj, hadj)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17])
+def test_device_tiny_worlds_match_the_oracle(n):
+    from .test_build_parity import S as S_
+    X, scal, loff, lab = small_world(n, 4, seed=n)
+    thr = [(S_, 1.0), (S_, 0.0)]
+    oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, 4, 8, thr, seed=1)
+    _say("device build, tiny world n =", n)
+    adj, entry = jag.jag_build_graph(X, scalar=scal, R=4, L_build=8, thresholds=thr, max_batch=1,
+                                     order=order, thr_values=tv, device=True)
+    assert entry == oentry and np.array_equal(adj, oadj)
+
+
+def test_device_duplicates_small_beams_and_eight_entries_match_the_oracle():
+    rng = np.random.default_rng(4)
+    X = np.repeat(rng.normal(size=(40, 8)).astype(np.float32), 5, axis=0)
+    scal = np.repeat(rng.integers(0, 4, size=40), 5).astype(np.int32)
+    loff = np.arange(X.shape[0] + 1, dtype=np.int64)
+    lab = np.zeros(X.shape[0], np.int32)
+    cases = [(X, scal, loff, lab, 1, 8, 16, [(S, 1.0), (S, 0.0), (LB, 0.0)])]
+    X2, s2, lo2, la2 = small_world(300, 12, seed=8)
+    cases += [(X2, s2, lo2, la2, 12, R, lb, thr) for R, lb, thr in
+              [(1, 1, [(S, 1.0)]), (6, 1, [(S, 1.0), (S, 0.0)]),
+               (16, 20, [(S, 1.0), (S, 0.5), (S, 0.2), (S, 0.05), (S, 0.0), (LB, 1.0), (LB, 0.0), (S | W, 3.0)])]]
+    for X_, s_, lo_, la_, voc, R, lb, thr in cases:
+        oadj, oentry, tv, order = oracle_graph(X_, s_, lo_, la_, R, lb, thr, seed=5)
+        _say("device build, rounds of one:", X_.shape, R, lb, len(thr))
+        adj, entry = jag.jag_build_graph(X_, scalar=s_, label_off=lo_, labels=la_, vocab=voc, R=R, L_build=lb,
+                                         thresholds=thr, max_batch=1, order=order, thr_values=tv, device=True)
+        assert entry == oentry and np.array_equal(adj, oadj), (X_.shape, R, lb, len(thr))
+
+
+@pytest.mark.parametrize("d", [1, 512])
+def test_device_build_smallest_and_largest_dimension(d):
+    X, scal, loff, lab = small_world(2000, d, seed=d)
+    kw = dict(scalar=scal, R=16, thresholds=[(S, 1.0), (S, 0.01), (S, 0.0)], seed=3)
+    hadj, he = jag.jag_build_graph(X, **kw)
+    _say("device build d =", d)
+    dadj, de = jag.jag_build_graph(X, device=True, **kw)
+    assert de == he and np.array_equal(dadj, hadj)
+
+
+def test_device_build_reports_a_round_too_large_for_its_buffers():
+    """Identical points all link to the same vertex; a round of 8,192 of them
+    gives it more in-links than one prune holds, which the host reports."""
+    X = np.zeros((20000, 8), np.float32)
+    scal = np.zeros(20000, np.int32)
+    _say("device build of 20,000 identical points, one round of 8,192")
+    with pytest.raises(jag.JagError, match="in-links"):
+        jag.jag_build_graph(X, scalar=scal, R=8, thresholds=[(S, 1.0)], max_batch=20000, device=True)
+    # rounds small enough stay within the buffers
+    adj, e = jag.jag_build_graph(X[:3000], scalar=scal[:3000], R=8, thresholds=[(S, 1.0)], max_batch=1000,
+                                 device=True)
+    hadj, he = jag.jag_build_graph(X[:3000], scalar=scal[:3000], R=8, thresholds=[(S, 1.0)], max_batch=1000)
+    assert e == he and np.array_equal(adj, hadj)
