@@ -398,8 +398,9 @@ jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_serv
 
 /* Queue n requests: Q host float[n][d], F host filters (pool as in
  * jag_encode_filters).  Filters are validated here; on EINVAL nothing is
- * queued (TABLE filters are not served: their distance tables do not fit the
- * fixed per-request records).  tickets_out[n] receives one ticket per request.  EBUSY when the
+ * queued.  A TABLE filter's distance table (2^nvar bytes) travels with its
+ * request and is packed, per batch, into a table area of the stream that runs
+ * it (pinned host and device memory grown on demand, outside hbm_budget_bytes).  tickets_out[n] receives one ticket per request.  EBUSY when the
  * queue would exceed queue_capacity (nothing queued). */
 jag_status jag_server_submit(jag_server *s, const float *Q, const jag_filter *F, int64_t n,
                              const int32_t *pool, int64_t pool_len, uint64_t *tickets_out);

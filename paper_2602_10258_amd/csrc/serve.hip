@@ -34,6 +34,7 @@ using clk = std::chrono::steady_clock;
 struct Request {
     uint64_t ticket;
     jag::FilterRecord rec;
+    std::vector<uint8_t> table;  // distance table of a TABLE filter (2^nvar bytes)
     std::vector<float> q;
     clk::time_point t_submit;
 };
@@ -57,6 +58,9 @@ struct Slot {
     jag::FilterRecord *d_rec = nullptr;
     int32_t *d_ids = nullptr, *d_cnt = nullptr;
     float *d_d = nullptr;
+    // distance tables of the batch's TABLE filters, grown on demand
+    uint8_t *h_tab = nullptr, *d_tab = nullptr;
+    size_t tab_cap = 0;
     std::vector<Request> batch;
     bool busy = false;
 };
@@ -92,9 +96,11 @@ void free_slot(Slot &s)
 {
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.event) (void)hipEventDestroy(s.event);
-    for (void *p : {(void *)s.h_q, (void *)s.h_rec, (void *)s.h_ids, (void *)s.h_cnt, (void *)s.h_d})
+    for (void *p : {(void *)s.h_q, (void *)s.h_rec, (void *)s.h_ids, (void *)s.h_cnt, (void *)s.h_d,
+                    (void *)s.h_tab})
         if (p) (void)hipHostFree(p);
-    for (void *p : {(void *)s.d_q, (void *)s.d_rec, (void *)s.d_ids, (void *)s.d_cnt, (void *)s.d_d})
+    for (void *p : {(void *)s.d_q, (void *)s.d_rec, (void *)s.d_ids, (void *)s.d_cnt, (void *)s.d_d,
+                    (void *)s.d_tab})
         if (p) (void)hipFree(p);
     s = Slot();
 }
@@ -126,13 +132,41 @@ bool launch(jag_server *S, Slot &s)
     jag::Index &ix = S->idx->ix;
     const int d = ix.d, k = S->P.k;
     const int n = (int)s.batch.size();
+    // TABLE filters: their distance tables go to the slot's table arena, and
+    // each record points there (table_off counts from the record's own address)
+    size_t tab_bytes = 0;
+    for (int i = 0; i < n; i++)
+        if (!s.batch[i].table.empty()) tab_bytes = (tab_bytes + 15) / 16 * 16 + s.batch[i].table.size();
+    if (tab_bytes > s.tab_cap) {
+        if (s.h_tab) (void)hipHostFree(s.h_tab);
+        if (s.d_tab) (void)hipFree(s.d_tab);
+        s.h_tab = nullptr;
+        s.d_tab = nullptr;
+        s.tab_cap = 0;
+        const size_t cap = std::max<size_t>(tab_bytes, (size_t)1 << 20);
+        if (!HIPOK(hipHostMalloc((void **)&s.h_tab, cap, hipHostMallocDefault)) ||
+            !HIPOK(hipMalloc((void **)&s.d_tab, cap))) {
+            jag::set_error("server table arena allocation failed");
+            return false;
+        }
+        s.tab_cap = cap;
+    }
+    size_t tpos = 0;
     for (int i = 0; i < n; i++) {
         std::memcpy(s.h_q + (size_t)i * d, s.batch[i].q.data(), sizeof(float) * d);
         s.h_rec[i] = s.batch[i].rec;
+        if (!s.batch[i].table.empty()) {
+            tpos = (tpos + 15) / 16 * 16;
+            std::memcpy(s.h_tab + tpos, s.batch[i].table.data(), s.batch[i].table.size());
+            s.h_rec[i].table_off = (int64_t)((intptr_t)(s.d_tab + tpos) - (intptr_t)(s.d_rec + i));
+            tpos += s.batch[i].table.size();
+        }
     }
     bool ok = HIPOK(hipMemcpyAsync(s.d_q, s.h_q, sizeof(float) * n * d, hipMemcpyHostToDevice, s.stream)) &&
               HIPOK(hipMemcpyAsync(s.d_rec, s.h_rec, sizeof(jag::FilterRecord) * n, hipMemcpyHostToDevice,
-                                   s.stream));
+                                   s.stream)) &&
+              (tab_bytes == 0 ||
+               HIPOK(hipMemcpyAsync(s.d_tab, s.h_tab, tab_bytes, hipMemcpyHostToDevice, s.stream)));
     if (ok) {
         jag_search_params sp = S->P.search;
         ok = jag::launch_search(ix, s.d_q, n, s.d_rec, k, sp, s.d_ids, s.d_d, s.d_cnt, s.stream) == JAG_OK;
@@ -296,9 +330,14 @@ jag_status jag_server_submit(jag_server *S, const float *Q, const jag_filter *F,
     }
     if (n == 0) return JAG_OK;
     const int d = S->idx->ix.d;
-    std::vector<jag::FilterRecord> rec(n);
-    jag_status st = jag::encode_filters(S->idx->ix, F, n, pool, pool_len, rec.data());
+    // records followed by the distance tables of any TABLE filters
+    int64_t bytes = 0;
+    jag_status st = jag::encoded_bytes(S->idx->ix, F, n, pool, pool_len, &bytes);
     if (st != JAG_OK) return st;
+    std::vector<uint8_t> enc((size_t)bytes);
+    st = jag::encode_filters_sized(S->idx->ix, F, n, pool, pool_len, enc.data(), bytes);
+    if (st != JAG_OK) return st;
+    const jag::FilterRecord *rec = reinterpret_cast<const jag::FilterRecord *>(enc.data());
     for (int64_t i = 0; i < n * d; i++)
         if (!std::isfinite(Q[i])) {
             set_error("query element %lld is not finite", (long long)i);
@@ -322,6 +361,11 @@ jag_status jag_server_submit(jag_server *S, const float *Q, const jag_filter *F,
         Request r;
         r.ticket = S->next_ticket++;
         r.rec = rec[i];
+        if (rec[i].type == jag::F_TABLE) {
+            const uint8_t *t = enc.data() + i * (int64_t)sizeof(jag::FilterRecord) + rec[i].table_off;
+            r.table.assign(t, t + ((size_t)1 << rec[i].nlit));
+            r.rec.table_off = 0;  // set at launch
+        }
         r.q.assign(Q + i * d, Q + (i + 1) * d);
         r.t_submit = now;
         tickets_out[i] = r.ticket;

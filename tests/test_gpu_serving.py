@@ -147,3 +147,46 @@ def test_concurrent_submitters(mixed_world):
         jag.jag_server_stop(s)
     for i, (ids, d, c, lat) in enumerate(res):
         assert np.array_equal(ids, ref["ids"][i])
+
+
+def test_table_filters_through_the_server():
+    """Truth-table filters travel with their distance tables: the server's
+    answers equal a direct search, mixed with other filter types, in batches
+    that hold several tables and alone."""
+    from .test_gpu_table_filters import _bool_world
+    w, A, adj, entry = _bool_world(10, nq=64, seed=7)
+    idx = jag.jag_build_from_graph(w.X, adj, entry, label_off=w.loff, labels=w.lab, vocab=w.vocab)
+    # every other query becomes a plain label filter
+    from workloads import FILTER_TABLE
+    kinds, pays = [], []
+    for i in range(w.nq):
+        if i % 2:
+            kinds.append(FILTER_LABEL)
+            pays.append(i % w.vocab)
+        else:
+            f = w.F[i]
+            p = w.pool[f[4]:f[4] + f[5]]
+            nv = int(p[0])
+            words = p[1 + nv:].astype(np.uint32)
+            tab = np.unpackbits(words.view(np.uint8), bitorder="little")[: 1 << nv].astype(bool)
+            kinds.append(FILTER_TABLE)
+            pays.append((p[1:1 + nv].tolist(), tab))
+    F, pool = encode_filters(kinds, pays)
+    ref = gpu_search(idx, w.Q, F, pool, 10, 48)
+    _say("table filters through the server")
+    s = jag.jag_server_start(idx, 10, jag.SearchParams(L=48), max_batch=8, n_streams=2, max_wait_us=50)
+    try:
+        t = jag.jag_server_submit(s, w.Q, F, pool)
+        mix = _collect(s, t)
+        alone = []
+        for i in range(0, w.nq, 5):
+            f = F[i:i + 1].copy()
+            p = pool[f[0, 4]:f[0, 4] + f[0, 5]].copy() if f[0, 0] == FILTER_TABLE else np.zeros(1, np.int32)
+            f[0, 4] = 0
+            alone.append((i, _collect(s, jag.jag_server_submit(s, w.Q[i:i + 1], f, p))[0]))
+    finally:
+        jag.jag_server_stop(s)
+    for q, (ids, d, c, lat) in enumerate(mix):
+        assert np.array_equal(ids, ref["ids"][q]) and c == ref["count"][q], q
+    for i, (ids, d, c, lat) in alone:
+        assert np.array_equal(ids, ref["ids"][i]) and c == ref["count"][i], i
