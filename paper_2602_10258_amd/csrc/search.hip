@@ -920,10 +920,11 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
 
 // ---------------------------------------------------------------- schedule
 // Longest-predicted-first order for the search pass of a two-pass learned
-// search: a stable counting sort of the queries by key = 1 + predicted
-// ladder index (0 = finished before the prediction point), largest first.
-// One workgroup; thread t owns the contiguous chunk [t*chunk, (t+1)*chunk)
-// of queries.
+// search: a counting sort of the queries by key = 1 + predicted ladder index
+// (0 = finished before the prediction point), largest first.  One workgroup;
+// thread t owns queries t, t + 512, t + 1024, ... (coalesced key reads);
+// within a class the order is (thread, then position), not the query order,
+// which no result depends on.
 constexpr int kOrderThreads = 512;
 constexpr int kOrderBins = JAG_LADDER_MAX + 1;
 
@@ -932,11 +933,9 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key
     __shared__ int32_t cnt[kOrderBins][kOrderThreads];
     __shared__ int32_t part[kOrderThreads];
     const int t = threadIdx.x;
-    const int64_t chunk = (nq + kOrderThreads - 1) / kOrderThreads;
-    const int64_t b0 = (int64_t)t * chunk;
-    const int64_t b1 = b0 + chunk < nq ? b0 + chunk : nq;
     for (int b = 0; b < kOrderBins; b++) cnt[b][t] = 0;
-    for (int64_t i = b0; i < b1; i++) {
+#pragma unroll 4
+    for (int64_t i = t; i < nq; i += kOrderThreads) {
         int k = key[i];
         k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
         cnt[k][t]++;
@@ -967,7 +966,8 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key
         run += v;
     }
     __syncthreads();
-    for (int64_t i = b0; i < b1; i++) {
+#pragma unroll 4
+    for (int64_t i = t; i < nq; i += kOrderThreads) {
         int k = key[i];
         k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
         perm[cnt[k][t]++] = (int32_t)i;
