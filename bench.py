@@ -534,7 +534,25 @@ def main():
         cands.append(dict(mode="fp8+rerank-fixed", ix=ix8, rec=rec8,
                           sp=jag.SearchParams(L=best_f8["L"], rerank_mult=4),
                           store=jag.STORE_FP8_E4M3, rerank=True, point=best_f8))
-    assert cands, "no configuration reached recall 0.95"
+    if not cands:
+        # nothing reaches the target: report the sweeps and the best recall seen
+        allp = [dict(r, mode=m) for m, rs in (("fp32-fixed", fixed), ("bf16+rerank-fixed", fixed16),
+                                              ("fp8+rerank-fixed", fixed8), ("learned+bf16+rerank", learned))
+                for r in rs]
+        top = max(allp, key=lambda r: r["recall"])
+        print(json.dumps({
+            "metric": METRIC, "value": None, "unit": "queries/s", "n_gpus": 1, "steps": 0,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{w.name}: {w.n} x {w.d} clustered vectors, {nq} queries "
+                                   f"({args.thresholds or w.meta.get('thresholds')}), k={k}, R={w.R}",
+                       "global_batch": nq, "filter_types": sorted({FILTER_NAMES[int(t)] for t in w.F[:, 0]})},
+            "note": "no configuration reached recall@10 = 0.95",
+            "best_recall": {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in top.items()},
+            "graph_build_seconds": build_times,
+            "sweeps": {"fixed": fixed, "bf16_rerank_fixed": fixed16, "fp8_rerank_fixed": fixed8,
+                       "learned": learned}}, default=float))
+        return
     op = max(cands, key=lambda c: c["point"]["qps"])
     log(f"operating point: {op['mode']} ({op['point']})")
 
