@@ -72,6 +72,7 @@ def parse():
                     help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--build", default="device", choices=["device", "host", "both"],
                     help="where the graph is built (both: host and device, checked equal, both timed)")
+    ap.add_argument("--R", type=int, default=0, help="out-degree bound of the graph (default: the workload's)")
     ap.add_argument("--thresholds", default=None,
                     help="comparator list of the build, e.g. 'labels:1,labels:0.01,labels:0' or "
                          "'weight:labels:0,weight:labels:1,weight:labels:10' (default: the workload's)")
@@ -334,6 +335,8 @@ def main():
     dev = torch.device("cuda:0")
     t0 = time.time()
     w = make_config(args.config, n=args.n, nq=args.nq)
+    if args.R:
+        w = dataclasses.replace(w, R=args.R)
     if args.filter_type is not None:
         keep = w.F[:, 0] == args.filter_type
         assert keep.any(), f"no queries of filter type {args.filter_type} in {w.name}"

@@ -100,7 +100,7 @@ typedef struct {
 } jag_threshold;
 
 typedef struct {
-    int32_t R;                /* out-degree bound ("deg", Algorithm 4), 1..64 */
+    int32_t R;                /* out-degree bound ("deg", Algorithm 4), 1..128 */
     int32_t L_build;          /* beam l_b of the insertion searches (Algorithm 3); 0 = 2R */
     float alpha;              /* pruning parameter (paper: 1.2) */
     int32_t n_thr;            /* |T|, 1..8 */

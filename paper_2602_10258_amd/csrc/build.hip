@@ -39,7 +39,7 @@ constexpr int kSW = 4;               // search waves per workgroup
 constexpr int kMaxLb = 256;          // largest build beam l_b
 constexpr int kSeenSlots = 1024;     // lossy seen-table of a search wave
 constexpr int kMaxCand = 4096;       // largest candidate set of one prune
-constexpr int kMaxOut = 80;          // chosen list of one prune (|T| * cap <= R + |T|)
+constexpr int kMaxOut = 136;         // chosen list of one prune (|T| * cap <= 0.9 R + |T|)
 constexpr uint32_t kExp = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
 
@@ -221,124 +221,129 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
     const int lb = a.lb;
     int32_t *expo = a.exp + task * a.hopcap;
     int nL = 0, hops = 0;
-    int32_t u = lane == 0 ? a.entry : -1;
+    int32_t v = -1;  // the vertex being expanded; -1 for the first step, whose candidate is the entry
 
     for (;;) {
-        // ---- candidates: one neighbour per lane
-        bool ok = u >= 0;
-        if (ok) {
-            const int s = seen_slot(u);
-            if (seen[s] == u) ok = false;
-            else seen[s] = u;
-        }
-        const bool full = nL == lb;
-        const uint64_t wk = full ? lkey[lb - 1] : ~0ull;
-        const int32_t wi = full ? (int32_t)((uint32_t)lid[lb - 1] & kIdMask) : 0x7FFFFFFF;
-        float f = 0.f;
-        if (ok && !wgt) {
-            f = first_dev(a, kind, t, p, u, 0.f);
-            if (full && __float_as_uint(f) > (uint32_t)(wk >> 32)) ok = false;  // cannot enter the beam
-        }
-        const uint64_t m = __ballot(ok);
-        const int nc = __popcll(m);
-        if (nc > 0) {
-            const int ci = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        // rows wider than a wave go in slices of 64 neighbours, merged in turn
+        for (int h = 0; h < (v < 0 ? 1 : a.R); h += 64) {
+            const int32_t u = v < 0 ? (lane == 0 ? a.entry : -1)
+                                    : (h + lane < a.R ? a.adj[(int64_t)v * a.R + h + lane] : -1);
+            // ---- candidates: one neighbour per lane
+            bool ok = u >= 0;
             if (ok) {
-                cu[ci] = u;
-                cf[ci] = f;
+                const int s = seen_slot(u);
+                if (seen[s] == u) ok = false;
+                else seen[s] = u;
             }
-            wave_sync();
-            for (int c0 = 0; c0 < nc; c0 += 32) {
-                const float *xb[4];
-                bool act[4];
-                int cc[4];
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    cc[k] = c0 + k * 8 + (lane >> 3);
-                    act[k] = cc[k] < nc;
-                    xb[k] = a.X + (int64_t)(act[k] ? cu[cc[k]] : 0) * a.d4;
+            const bool full = nL == lb;
+            const uint64_t wk = full ? lkey[lb - 1] : ~0ull;
+            const int32_t wi = full ? (int32_t)((uint32_t)lid[lb - 1] & kIdMask) : 0x7FFFFFFF;
+            float f = 0.f;
+            if (ok && !wgt) {
+                f = first_dev(a, kind, t, p, u, 0.f);
+                if (full && __float_as_uint(f) > (uint32_t)(wk >> 32)) ok = false;  // cannot enter the beam
+            }
+            const uint64_t m = __ballot(ok);
+            const int nc = __popcll(m);
+            if (nc > 0) {
+                const int ci = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+                if (ok) {
+                    cu[ci] = u;
+                    cf[ci] = f;
                 }
-                float d2[4];
-                dist8x4(xp, xb, a.d4, lane & 7, d2);
-#pragma unroll
-                for (int k = 0; k < 4; k++)
-                    if (act[k] && (lane & 7) == 0) cd2[cc[k]] = d2[k];
-            }
-            wave_sync();
-            // ---- one lane per candidate: key, beam test, repeat test
-            bool ok2 = lane < nc;
-            uint64_t key = 0;
-            int32_t id = 0;
-            int lbp = 0;
-            if (ok2) {
-                id = cu[lane];
-                const float d2 = cd2[lane];
-                const float ff = wgt ? first_dev(a, kind, t, p, id, d2) : cf[lane];
-                key = ((uint64_t)__float_as_uint(ff) << 32) | __float_as_uint(d2);
-                if (full && !key_less(key, id, wk, wi)) ok2 = false;
-                else {
-                    int lo = 0, hi = nL;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (key_less(lkey[mid], (int32_t)((uint32_t)lid[mid] & kIdMask), key, id)) lo = mid + 1;
-                        else hi = mid;
+                wave_sync();
+                for (int c0 = 0; c0 < nc; c0 += 32) {
+                    const float *xb[4];
+                    bool act[4];
+                    int cc[4];
+    #pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        cc[k] = c0 + k * 8 + (lane >> 3);
+                        act[k] = cc[k] < nc;
+                        xb[k] = a.X + (int64_t)(act[k] ? cu[cc[k]] : 0) * a.d4;
                     }
-                    lbp = lo;
-                    if (lo < nL && lkey[lo] == key && (int32_t)((uint32_t)lid[lo] & kIdMask) == id) ok2 = false;
+                    float d2[4];
+                    dist8x4(xp, xb, a.d4, lane & 7, d2);
+    #pragma unroll
+                    for (int k = 0; k < 4; k++)
+                        if (act[k] && (lane & 7) == 0) cd2[cc[k]] = d2[k];
                 }
-            }
-            const uint64_t m2 = __ballot(ok2);
-            const int nc2 = __popcll(m2);
-            if (nc2 > 0) {
-                const int c2 = __builtin_amdgcn_mbcnt_hi((uint32_t)(m2 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m2, 0));
+                wave_sync();
+                // ---- one lane per candidate: key, beam test, repeat test
+                bool ok2 = lane < nc;
+                uint64_t key = 0;
+                int32_t id = 0;
+                int lbp = 0;
                 if (ok2) {
-                    ck[c2] = key;
-                    cid[c2] = id;
-                }
-                wave_sync();
-                int rank = 0;
-                if (ok2)
-                    for (int j = 0; j < nc2; j++) rank += key_less(ck[j], cid[j], key, id) ? 1 : 0;
-                if (ok2) spos[rank] = lbp;  // beam positions of the candidates in key order
-                // beam entries into registers before anything moves
-                uint64_t ek[kMaxLb / 64];
-                int32_t ei[kMaxLb / 64];
-#pragma unroll
-                for (int r = 0; r < kMaxLb / 64; r++) {
-                    const int i = r * 64 + lane;
-                    if (i < nL) {
-                        ek[r] = lkey[i];
-                        ei[r] = lid[i];
-                    }
-                }
-                wave_sync();
-#pragma unroll
-                for (int r = 0; r < kMaxLb / 64; r++) {
-                    const int i = r * 64 + lane;
-                    if (i < nL) {
-                        // candidates before entry i: those whose beam position is <= i
-                        int lo = 0, hi = nc2;
+                    id = cu[lane];
+                    const float d2 = cd2[lane];
+                    const float ff = wgt ? first_dev(a, kind, t, p, id, d2) : cf[lane];
+                    key = ((uint64_t)__float_as_uint(ff) << 32) | __float_as_uint(d2);
+                    if (full && !key_less(key, id, wk, wi)) ok2 = false;
+                    else {
+                        int lo = 0, hi = nL;
                         while (lo < hi) {
                             const int mid = (lo + hi) >> 1;
-                            if (spos[mid] <= i) lo = mid + 1;
+                            if (key_less(lkey[mid], (int32_t)((uint32_t)lid[mid] & kIdMask), key, id)) lo = mid + 1;
                             else hi = mid;
                         }
-                        const int np = i + lo;
-                        if (np < lb) {
-                            lkey[np] = ek[r];
-                            lid[np] = ei[r];
+                        lbp = lo;
+                        if (lo < nL && lkey[lo] == key && (int32_t)((uint32_t)lid[lo] & kIdMask) == id) ok2 = false;
+                    }
+                }
+                const uint64_t m2 = __ballot(ok2);
+                const int nc2 = __popcll(m2);
+                if (nc2 > 0) {
+                    const int c2 = __builtin_amdgcn_mbcnt_hi((uint32_t)(m2 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m2, 0));
+                    if (ok2) {
+                        ck[c2] = key;
+                        cid[c2] = id;
+                    }
+                    wave_sync();
+                    int rank = 0;
+                    if (ok2)
+                        for (int j = 0; j < nc2; j++) rank += key_less(ck[j], cid[j], key, id) ? 1 : 0;
+                    if (ok2) spos[rank] = lbp;  // beam positions of the candidates in key order
+                    // beam entries into registers before anything moves
+                    uint64_t ek[kMaxLb / 64];
+                    int32_t ei[kMaxLb / 64];
+    #pragma unroll
+                    for (int r = 0; r < kMaxLb / 64; r++) {
+                        const int i = r * 64 + lane;
+                        if (i < nL) {
+                            ek[r] = lkey[i];
+                            ei[r] = lid[i];
                         }
                     }
-                }
-                if (ok2) {
-                    const int np = lbp + rank;
-                    if (np < lb) {
-                        lkey[np] = key;
-                        lid[np] = id;
+                    wave_sync();
+    #pragma unroll
+                    for (int r = 0; r < kMaxLb / 64; r++) {
+                        const int i = r * 64 + lane;
+                        if (i < nL) {
+                            // candidates before entry i: those whose beam position is <= i
+                            int lo = 0, hi = nc2;
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (spos[mid] <= i) lo = mid + 1;
+                                else hi = mid;
+                            }
+                            const int np = i + lo;
+                            if (np < lb) {
+                                lkey[np] = ek[r];
+                                lid[np] = ei[r];
+                            }
+                        }
                     }
+                    if (ok2) {
+                        const int np = lbp + rank;
+                        if (np < lb) {
+                            lkey[np] = key;
+                            lid[np] = id;
+                        }
+                    }
+                    nL = min(lb, nL + nc2);
+                    wave_sync();
                 }
-                nL = min(lb, nL + nc2);
-                wave_sync();
             }
         }
         // ---- the first unexpanded entry of the beam
@@ -353,7 +358,7 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
             }
         }
         if (pi < 0 || hops >= a.hopcap) break;
-        const int32_t v = (int32_t)((uint32_t)lid[pi] & kIdMask);
+        v = (int32_t)((uint32_t)lid[pi] & kIdMask);
         wave_sync();
         if (lane == 0) {
             lid[pi] = (int32_t)((uint32_t)v | kExp);
@@ -361,7 +366,6 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
         }
         hops++;
         wave_sync();
-        u = lane < a.R ? a.adj[(int64_t)v * a.R + lane] : -1;
     }
     if (lane == 0) {
         a.expcnt[task] = hops;
@@ -374,7 +378,7 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
 // member rows.
 __host__ __device__ constexpr int prune_wave_bytes(int P, int memf)
 {
-    return memf * 4 + P * (4 + 4 + 4 + 2 + 1) + kMaxOut * 4 + 64 * 4 + 16;
+    return memf * 4 + P * (4 + 4 + 4 + 2 + 1) + kMaxOut * 4 + 128 * 4 + 16;
 }
 
 // Ascending bitonic sort of ids in LDS (P a power of two, padded with INT_MAX).
@@ -605,7 +609,7 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
     float *fst = pd2 + P;
     int32_t *outl = reinterpret_cast<int32_t *>(fst + P);
     int32_t *mid = outl + kMaxOut;
-    uint16_t *ord = reinterpret_cast<uint16_t *>(mid + 64);
+    uint16_t *ord = reinterpret_cast<uint16_t *>(mid + 128);
     uint8_t *flg = reinterpret_cast<uint8_t *>(ord + P);
 
     if (mode == 0) {

@@ -40,7 +40,7 @@ static_assert(sizeof(FilterRecord) == JAG_FILTER_RECORD_BYTES, "record size");
 
 // ---------------------------------------------------------------- index
 constexpr int kMaxDim = 512;
-constexpr int kMaxR = 64;
+constexpr int kMaxR = 128;
 constexpr int kMaxLabelsPerItem = 16;
 constexpr int kPredParams = 5313;
 

@@ -567,7 +567,7 @@ __device__ float predict(const Lds &s, const uint16_t *P)
 }
 
 // WPE: occupancy target (waves per SIMD) the register allocator works to.
-template <int STORE, int G, int CH, int WPE>
+template <int STORE, int G, int CH, int WPE, int SL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -642,32 +642,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         }
         hops++;
         // one row holds the neighbour ids and their attribute words: both
-        // loads are issued together, before the ids are known
+        // loads are issued together, before the ids are known.  Rows wider
+        // than a wave (SL = 2: R up to 128) go in slices of 64 neighbours,
+        // each merged in turn (one slice after the other keeps the same best l_s)
         const int32_t *row = a.adj + (int64_t)p * a.adj_words;
-        int32_t u = -1;
-        ItemAttr at;
-        if (lane < a.R) {
-            u = row[lane];
-            load_row_attr(at, f, row, lane, a);
-        }
-        bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
-        uint32_t df = fresh ? dist_f(f, tab, at, a) : 0u;
-        nattr += __popcll(ballot64(fresh));
-        if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
-        uint64_t bm = ballot64(fresh);
-        int m = __popcll(bm);
-        if (fresh) {
-            int slot = lanes_below(bm);
-            s.cid[slot] = u;
-            s.cdf[slot] = df;
-        }
-        __syncthreads();
         int minpos = INT_MAX;
-        if (m > 0) {
-            eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
+#pragma unroll
+        for (int h = 0; h < SL * 64; h += 64) {
+            if (h >= a.R) break;
+            int32_t u = -1;
+            ItemAttr at;
+            if (h + lane < a.R) {
+                u = row[h + lane];
+                load_row_attr(at, f, row, h + lane, a);
+            }
+            bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
+            uint32_t df = fresh ? dist_f(f, tab, at, a) : 0u;
+            nattr += __popcll(ballot64(fresh));
+            if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
+            uint64_t bm = ballot64(fresh);
+            int m = __popcll(bm);
+            if (fresh) {
+                int slot = lanes_below(bm);
+                s.cid[slot] = u;
+                s.cdf[slot] = df;
+            }
             __syncthreads();
-            ndist += m;
-            cnt = merge_candidates(s, m, cnt, ls, &minpos);
+            if (m > 0) {
+                eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
+                __syncthreads();
+                ndist += m;
+                int mp = INT_MAX;
+                cnt = merge_candidates(s, m, cnt, ls, &mp);
+                minpos = mp < minpos ? mp : minpos;
+            }
         }
         hint = minpos < hint + 1 ? minpos : hint + 1;
         if (!predicted && hops == 4) {
@@ -997,30 +1005,32 @@ int pick_group(int stride) { return stride <= 512 ? 4 : 16; }
 using SearchFn = void (*)(SearchArgs);
 using ExactFn = void (*)(SearchArgs, int64_t);
 
-template <int STORE, int G, int WPE>
+template <int STORE, int G, int WPE, int SL>
 SearchFn search_for_ch(int ch)
 {
     switch (ch) {
-    case 1: return search_kernel<STORE, G, 1, WPE>;
-    case 2: return search_kernel<STORE, G, 2, WPE>;
-    case 3: return search_kernel<STORE, G, 3, WPE>;
-    case 4: return search_kernel<STORE, G, 4, WPE>;
-    case 5: return search_kernel<STORE, G, 5, WPE>;
-    case 6: return search_kernel<STORE, G, 6, WPE>;
-    case 7: return search_kernel<STORE, G, 7, WPE>;
-    case 8: return search_kernel<STORE, G, 8, WPE>;
+    case 1: return search_kernel<STORE, G, 1, WPE, SL>;
+    case 2: return search_kernel<STORE, G, 2, WPE, SL>;
+    case 3: return search_kernel<STORE, G, 3, WPE, SL>;
+    case 4: return search_kernel<STORE, G, 4, WPE, SL>;
+    case 5: return search_kernel<STORE, G, 5, WPE, SL>;
+    case 6: return search_kernel<STORE, G, 6, WPE, SL>;
+    case 7: return search_kernel<STORE, G, 7, WPE, SL>;
+    case 8: return search_kernel<STORE, G, 8, WPE, SL>;
     }
     return nullptr;
 }
 
-template <int WPE>
-SearchFn pick_search_wpe(int store, int G, int ch)
+template <int WPE, int SL>
+SearchFn pick_search_sl(int store, int G, int ch)
 {
     if (store == JAG_STORE_F32)
-        return G == 4 ? search_for_ch<JAG_STORE_F32, 4, WPE>(ch) : search_for_ch<JAG_STORE_F32, 16, WPE>(ch);
+        return G == 4 ? search_for_ch<JAG_STORE_F32, 4, WPE, SL>(ch) : search_for_ch<JAG_STORE_F32, 16, WPE, SL>(ch);
     if (store == JAG_STORE_BF16)
-        return G == 4 ? search_for_ch<JAG_STORE_BF16, 4, WPE>(ch) : search_for_ch<JAG_STORE_BF16, 16, WPE>(ch);
-    return G == 4 ? search_for_ch<JAG_STORE_FP8_E4M3, 4, WPE>(ch) : search_for_ch<JAG_STORE_FP8_E4M3, 16, WPE>(ch);
+        return G == 4 ? search_for_ch<JAG_STORE_BF16, 4, WPE, SL>(ch)
+                      : search_for_ch<JAG_STORE_BF16, 16, WPE, SL>(ch);
+    return G == 4 ? search_for_ch<JAG_STORE_FP8_E4M3, 4, WPE, SL>(ch)
+                  : search_for_ch<JAG_STORE_FP8_E4M3, 16, WPE, SL>(ch);
 }
 
 // All modes use the build for 5 waves per SIMD (at most 96 VGPRs; the
@@ -1031,11 +1041,13 @@ SearchFn pick_search_wpe(int store, int G, int ch)
 // for learned search.)
 constexpr int kWavesPerSimd = 5;
 
-SearchFn pick_search(int store, int stride, int /*mode*/)
+// Rows of more than 64 neighbours take the two-slice build (the one-slice
+// build has no slice loop, which keeps its register allocation).
+SearchFn pick_search(int store, int stride, int R)
 {
     int G = pick_group(stride);
     int ch = stride / (16 * G);
-    return pick_search_wpe<kWavesPerSimd>(store, G, ch);
+    return R <= 64 ? pick_search_sl<kWavesPerSimd, 1>(store, G, ch) : pick_search_sl<kWavesPerSimd, 2>(store, G, ch);
 }
 
 template <int G>
@@ -1334,7 +1346,7 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
     int H = S.hash_log2 ? (1 << S.hash_log2) : kDefaultHash;
     a.Lcap = Lcap;
     a.Hmask = H - 1;
-    fn = pick_search(ix.store, ix.vec_stride, S.learned);
+    fn = pick_search(ix.store, ix.vec_stride, ix.R);
     if (!fn) {
         set_error("no kernel for row stride %d", ix.vec_stride);
         return JAG_EUNSUPPORTED;

@@ -23,6 +23,7 @@ CASES = {
     "mixed5": (1000, 33, 10, 20, [(S, 1.0), (LB, 0.1), (S, 0.0), (LB, 0.0), (S, 0.2)]),
     "weight": (400, 16, 12, 24, [(S | W, 0.0), (S | W, 2.0), (S | W, 50.0)]),
     "wide": (1500, 40, 20, 40, [(S, 1.0), (S, 0.01), (S, 0.0)]),
+    "deg128": (1200, 16, 128, 160, [(S, 1.0), (LB, 0.0)]),
 }
 
 

@@ -29,7 +29,7 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("case", ["scalar", "labels", "mixed5", "weight"])
+@pytest.mark.parametrize("case", ["scalar", "labels", "mixed5", "weight", "deg128"])
 def test_device_rounds_of_one_give_the_oracle_graph(case):
     n, d, R, lb, thr = CASES[case]
     X, scal, loff, lab = small_world(n, d, seed=len(case))
@@ -48,6 +48,9 @@ def _world(name):
     if name == "c2":
         w = make_config("c2", n=20000, nq=10)
         return w, dict(scalar=w.scalar), 64, [(S, 1.0), (S, 0.01), (S, 0.0)]
+    if name == "c2r128":
+        w = make_config("c2", n=20000, nq=10)
+        return w, dict(scalar=w.scalar), 128, [(S, 1.0), (S, 0.01), (S, 0.0)]
     if name == "c2w":
         w = make_config("c2", n=20000, nq=10)
         return w, dict(scalar=w.scalar), 48, [(S | W, 0.0), (S | W, 10.0), (S | W, 1000.0)]
@@ -61,7 +64,7 @@ def _world(name):
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c2w", "c3", "c5"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c2w", "c3", "c5", "c2r128"])
 def test_device_build_equals_host_build(name):
     w, attrs, R, thr = _world(name)
     kw = dict(R=R, thresholds=thr, seed=11, **attrs)

@@ -88,6 +88,37 @@ def test_all_filter_types_match_oracle(mixed_world, L):
     assert n_ex >= 0.8 * w.nq
 
 
+@pytest.fixture(scope="module")
+def deg128_graph(mixed_world):
+    """The mixed world's points in a graph of out-degree up to 128 (rows span
+    two 64-neighbour slices of the search)."""
+    w = mixed_world[0]
+    S, LB = jag.ATTR_SCALAR, jag.ATTR_LABELS
+    return jag.jag_build_graph(w.X, scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab, R=128,
+                               thresholds=[(S, 1.0), (S, 0.01), (S, 0.0), (LB, 0.0)], seed=1, n_threads=8)
+
+
+@pytest.mark.parametrize("store,L,rerank", [(jag.STORE_F32, 16, 0), (jag.STORE_F32, 130, 0),
+                                            (jag.STORE_BF16, 64, 4)])
+def test_degree_128_rows_match_oracle(mixed_world, deg128_graph, store, L, rerank):
+    w, A, _, _ = mixed_world
+    adj, entry = deg128_graph
+    assert (adj >= 0).sum(1).max() > 64
+    _say("degree-128 rows, store", store, "L", L)
+    idx = _index(w, adj, entry, store=store, keep_f32=True)
+    g = gpu_search(idx, w.Q, w.F, w.pool, 10, L, rerank_mult=rerank)
+    base = w.X if store == jag.STORE_F32 else O.bf16_decode(O.bf16_encode(w.X))
+    orc = O.search(base, adj, entry, A, w.Q, w.F, w.pool, L, 10, rerank=w.X if rerank else None,
+                   rerank_mult=rerank or 4)
+    tau = tau_for(store, w.d, rerank_d=w.d if rerank else None)
+    n_ex, n_fl, n_fd = compare(g["ids"], g["d2"], g["count"], orc, tau, _valid_fn(w, w.F, w.pool),
+                               f"R=128 store={store} L={L}")
+    _say(f"exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
+    assert n_ex >= 0.8 * w.nq
+    same = orc.margin >= tau
+    assert np.array_equal(g["stats"][same, 0], orc.hops[same])
+
+
 @pytest.mark.parametrize("store", [jag.STORE_F32, jag.STORE_BF16])
 def test_wide_label_rows_match_oracle(store):
     """Items with up to 10 Zipf labels of 1,000 (16-wide label rows inlined in
