@@ -211,8 +211,8 @@ typedef struct {
  * store are then placed in device memory of the current device.
  * Errors: EINVAL (n < 1, d < 1, d > 512, bad params, attributes, order or
  * thresholds; L_build > 256 on the device), ENOMEM, EDEVICE, EUNSUPPORTED
- * (device rounds only: one insertion expanding more than 4096 vertices over
- * all its searches, or a vertex gaining more than 4096 - R in-links in one
+ * (device rounds only: one insertion expanding more than 65536 vertices over
+ * all its searches, or a vertex gaining more than 65536 - R in-links in one
  * round; a smaller max_batch avoids the latter).
  */
 jag_status jag_build(const float *X, int64_t n, int32_t d, const jag_attrs *A,

@@ -38,7 +38,8 @@ namespace {
 constexpr int kSW = 4;               // search waves per workgroup
 constexpr int kMaxLb = 256;          // largest build beam l_b
 constexpr int kSeenSlots = 1024;     // lossy seen-table of a search wave
-constexpr int kMaxCand = 4096;       // largest candidate set of one prune
+constexpr int kMaxCand = 4096;       // largest candidate set of one prune in LDS
+constexpr int kMaxBigCand = 65536;   // largest in global memory (16-bit positions)
 constexpr int kMaxOut = 136;         // chosen list of one prune (|T| * cap <= 0.9 R + |T|)
 constexpr uint32_t kExp = 0x80000000u;
 constexpr uint32_t kIdMask = 0x7FFFFFFFu;
@@ -76,7 +77,8 @@ struct BArgs {
     int32_t *segoff;       // [n]
     int32_t *touched;      // [maxnb * R]
     int32_t *inl;          // [maxnb * R]
-    int32_t *ctr;          // [0] targets, [1] in-link cursor, [2] largest in-count, [3] largest union
+    int32_t *ctr;          // [0] targets, [1] in-link cursor, [2] largest in-count, [3] largest union,
+                           // [4] insertions and [6] targets above kMaxCand candidates, [5] scratch slots
 };
 
 __device__ __forceinline__ bool key_less(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib)
@@ -175,6 +177,21 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The prune's arrays live in LDS (GM = false) or, for candidate sets too
+// large for LDS, in global scratch (GM = true), where the lanes of the wave
+// exchange data through memory and order it with workgroup-scope fences.
+template <bool GM>
+__device__ __forceinline__ void wsync()
+{
+    if (GM) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        wave_sync();
+    }
 }
 
 // Bytes of LDS one search wave uses.
@@ -370,7 +387,11 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
     if (lane == 0) {
         a.expcnt[task] = hops;
         const unsigned long long old = atomicAdd(&a.ptot[bi], (1ull << 32) + (unsigned long long)hops);
-        if ((int)(old >> 32) == a.nT - 1) atomicMax(&a.ctr[3], (int32_t)(old & 0xFFFFFFFFull) + hops);
+        if ((int)(old >> 32) == a.nT - 1) {
+            const int32_t total = (int32_t)(old & 0xFFFFFFFFull) + hops;
+            atomicMax(&a.ctr[3], total);
+            if (total > kMaxCand) atomicAdd(&a.ctr[4], 1);  // prunes for the global-memory pass
+        }
     }
 }
 
@@ -381,7 +402,8 @@ __host__ __device__ constexpr int prune_wave_bytes(int P, int memf)
     return memf * 4 + P * (4 + 4 + 4 + 2 + 1) + kMaxOut * 4 + 128 * 4 + 16;
 }
 
-// Ascending bitonic sort of ids in LDS (P a power of two, padded with INT_MAX).
+// Ascending bitonic sort of ids (P a power of two, padded with INT_MAX).
+template <bool GM>
 __device__ void sort_ids(int32_t *x, int P, int lane)
 {
     for (int k = 2; k <= P; k <<= 1)
@@ -397,11 +419,12 @@ __device__ void sort_ids(int32_t *x, int P, int lane)
                     }
                 }
             }
-            wave_sync();
+            wsync<GM>();
         }
 }
 
 // Drop INT_MAX padding and repeats from sorted x[0..P); returns the count.
+template <bool GM>
 __device__ int unique_ids(int32_t *x, int P, int lane)
 {
     int out = 0;
@@ -415,10 +438,10 @@ __device__ int unique_ids(int32_t *x, int P, int lane)
         prev_last = __shfl(xi, 63);
         const uint64_t m = __ballot(keep);
         const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-        wave_sync();
+        wsync<GM>();
         if (keep) x[out + r] = xi;
         out += __popcll(m);
-        wave_sync();
+        wsync<GM>();
     }
     return out;
 }
@@ -461,7 +484,7 @@ __device__ __forceinline__ float dist_reg(const float4 (&r)[CH], const float *__
 // member it accepts being tested against the candidates after it.  Member rows
 // sit in LDS (mem) when they fit, else they are read from X.  Writes the
 // first R chosen ids into v's row.
-template <int CH, int U>
+template <int CH, int U, bool GM>
 __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float *pd2, float *fst,
                            uint16_t *ord, uint8_t *flg, int32_t *outl, int32_t *mid, float *mem, int lane)
 {
@@ -482,7 +505,7 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
             if (cc[k] < nv && g == 0) pd2[cc[k]] = d2[k];
     }
     for (int j = lane; j < nv; j += 64) flg[j] = 0;
-    wave_sync();
+    wsync<GM>();
     int nout = 0;
     for (int ti = 0; ti < a.nT; ti++) {
         const int kind = a.kinds[ti];
@@ -491,7 +514,7 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
         int P2 = 64;
         while (P2 < nv) P2 <<= 1;
         for (int j = lane; j < P2; j += 64) ord[j] = (uint16_t)j;
-        wave_sync();
+        wsync<GM>();
         // bitonic sort of positions by (first, d2, id); positions >= nv last
         for (int k = 2; k <= P2; k <<= 1)
             for (int jj = k >> 1; jj > 0; jj >>= 1) {
@@ -516,7 +539,7 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
                         }
                     }
                 }
-                wave_sync();
+                wsync<GM>();
             }
         int nm = 0;  // members of this bucket
         for (int c0 = 0; c0 < nv && nm < a.cap; c0 += 8 * U) {
@@ -573,7 +596,7 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
                         }
                     }
                     nm++;
-                    wave_sync();
+                    wsync<GM>();
                     if (nm >= a.cap) break;
                     // the candidates after it in this chunk meet the new member
                     const float *mrow = mem ? mem + (size_t)(nm - 1) * a.d4 : a.X + (int64_t)V[o] * a.d4;
@@ -588,7 +611,7 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
                 if (nm >= a.cap) break;
             }
         }
-        wave_sync();
+        wsync<GM>();
     }
     const int m = min(nout, a.R);
     int32_t *row = a.adj + v * a.R;
@@ -597,14 +620,35 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
 
 // Mode 0: prune the union of a new point's expanded sets into its row.
 // Mode 1: merge a target's new in-links into its row (re-pruned above R).
-template <int CH, int U>
+// GM = false: prunes of at most kMaxCand candidates, arrays in LDS (P slots,
+// memf floats of member rows); blocks with larger candidate sets return at
+// once.  GM = true: only those larger prunes, each with P slots in its own
+// gbytes of global scratch (slots handed out by ctr[5]) and member rows read
+// from X.  The two passes together prune every block exactly once.
+template <int CH, int U, bool GM>
 __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, int32_t mode, int32_t P,
-                                                         int32_t memf)
+                                                         int32_t memf, unsigned char *gs, int64_t gbytes)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
-    float *mem = memf > 0 ? reinterpret_cast<float *>(smem) : nullptr;
-    int32_t *V = reinterpret_cast<int32_t *>(smem + (size_t)memf * 4);
+    bool big;
+    if (mode == 0) {
+        int tot = 0;
+        for (int ti = 0; ti < a.nT; ti++) tot += a.expcnt[(int64_t)blockIdx.x * a.nT + ti];
+        big = tot > kMaxCand;
+    } else {
+        big = a.incnt[a.touched[blockIdx.x]] + a.R > kMaxCand;
+    }
+    if (big != GM) return;
+    unsigned char *base = smem;
+    if (GM) {
+        int slot = 0;
+        if (lane == 0) slot = atomicAdd(&a.ctr[5], 1);
+        slot = __shfl(slot, 0);
+        base = gs + (size_t)slot * (size_t)gbytes;
+    }
+    float *mem = memf > 0 ? reinterpret_cast<float *>(base) : nullptr;
+    int32_t *V = reinterpret_cast<int32_t *>(base + (size_t)memf * 4);
     float *pd2 = reinterpret_cast<float *>(V + P);
     float *fst = pd2 + P;
     int32_t *outl = reinterpret_cast<int32_t *>(fst + P);
@@ -625,10 +669,10 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
         int P2 = 64;
         while (P2 < tot) P2 <<= 1;
         for (int j = tot + lane; j < P2; j += 64) V[j] = 0x7FFFFFFF;
-        wave_sync();
-        sort_ids(V, P2, lane);
-        const int nv = unique_ids(V, P2, lane);
-        prune_core<CH, U>(a, p, V, nv, pd2, fst, ord, flg, outl, mid, mem, lane);
+        wsync<GM>();
+        sort_ids<GM>(V, P2, lane);
+        const int nv = unique_ids<GM>(V, P2, lane);
+        prune_core<CH, U, GM>(a, p, V, nv, pd2, fst, ord, flg, outl, mid, mem, lane);
         return;
     }
     const int64_t v = a.touched[blockIdx.x];
@@ -643,8 +687,8 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
     int P2 = 64;
     while (P2 < cnt) P2 <<= 1;
     for (int j = lane; j < P2; j += 64) V[j] = j < cnt ? src[j] : 0x7FFFFFFF;
-    wave_sync();
-    sort_ids(V, P2, lane);
+    wsync<GM>();
+    sort_ids<GM>(V, P2, lane);
     // in-links not already in the row, in id order
     int nnew = 0;
     for (int c0 = 0; c0 < cnt; c0 += 64) {
@@ -655,10 +699,10 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
             if (row[r] == x) fresh = false;
         const uint64_t m = __ballot(fresh);
         const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-        wave_sync();
+        wsync<GM>();
         if (fresh) V[nnew + r] = x;
         nnew += __popcll(m);
-        wave_sync();
+        wsync<GM>();
     }
     if (deg + nnew <= a.R) {
         for (int j = lane; j < nnew; j += 64) row[deg + j] = V[j];
@@ -669,10 +713,10 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
         int P3 = 64;
         while (P3 < tot) P3 <<= 1;
         for (int j = tot + lane; j < P3; j += 64) V[j] = 0x7FFFFFFF;
-        wave_sync();
-        sort_ids(V, P3, lane);
-        const int nv = unique_ids(V, P3, lane);
-        prune_core<CH, U>(a, v, V, nv, pd2, fst, ord, flg, outl, mid, mem, lane);
+        wsync<GM>();
+        sort_ids<GM>(V, P3, lane);
+        const int nv = unique_ids<GM>(V, P3, lane);
+        prune_core<CH, U, GM>(a, v, V, nv, pd2, fst, ord, flg, outl, mid, mem, lane);
     }
     if (lane == 0) {
         a.incnt[v] = 0;
@@ -710,6 +754,8 @@ __global__ void rev_offset_kernel(BArgs a)
     base = __shfl(base, 63);
     if (t < nt) a.segoff[a.touched[t]] = base + incl - c;
     if (lane == 0) atomicMax(&a.ctr[2], mx);
+    const uint64_t big = __ballot(t < nt && c + a.R > kMaxCand);  // prunes for the global-memory pass
+    if (lane == 0 && big) atomicAdd(&a.ctr[6], (int)__popcll(big));
 }
 
 __global__ void rev_fill_kernel(BArgs a, int64_t pos0, int32_t nb)
@@ -741,19 +787,50 @@ struct DevBufs {
     }
 };
 
-// Member rows go to LDS when the wave's LDS stays within 64 KB.
+template <bool GM>
+void launch_prune_kind(const BArgs &a, dim3 gr, size_t lds, int64_t pos, int32_t mode, int32_t P, int32_t memf,
+                       unsigned char *gs, int64_t gbytes)
+{
+    const dim3 bl(64);
+    // a candidate row takes ceil(d4 / 32) float4 per lane; four candidates per
+    // group of eight lanes up to d4 = 128, one above
+    if (a.d4 <= 64)
+        hipLaunchKernelGGL((build_prune_kernel<2, 4, GM>), gr, bl, lds, 0, a, pos, mode, P, memf, gs, gbytes);
+    else if (a.d4 <= 96)
+        hipLaunchKernelGGL((build_prune_kernel<3, 4, GM>), gr, bl, lds, 0, a, pos, mode, P, memf, gs, gbytes);
+    else if (a.d4 <= 128)
+        hipLaunchKernelGGL((build_prune_kernel<4, 4, GM>), gr, bl, lds, 0, a, pos, mode, P, memf, gs, gbytes);
+    else
+        hipLaunchKernelGGL((build_prune_kernel<16, 1, GM>), gr, bl, lds, 0, a, pos, mode, P, memf, gs, gbytes);
+}
+
+// The LDS pass over all blocks (prunes of up to kMaxCand candidates, P slots;
+// member rows go to LDS when the wave's LDS stays within 64 KB).
 hipError_t launch_prune(const BArgs &a, int32_t grid, int64_t pos, int32_t mode, int32_t P)
 {
     const int memf = prune_wave_bytes(P, a.cap * a.d4) <= 65536 ? a.cap * a.d4 : 0;
-    const size_t lds = (size_t)prune_wave_bytes(P, memf);
-    const dim3 gr((unsigned)grid), bl(64);
-    // a candidate row takes ceil(d4 / 32) float4 per lane; four candidates per
-    // group of eight lanes up to d4 = 128, one above
-    if (a.d4 <= 64) hipLaunchKernelGGL((build_prune_kernel<2, 4>), gr, bl, lds, 0, a, pos, mode, P, memf);
-    else if (a.d4 <= 96) hipLaunchKernelGGL((build_prune_kernel<3, 4>), gr, bl, lds, 0, a, pos, mode, P, memf);
-    else if (a.d4 <= 128) hipLaunchKernelGGL((build_prune_kernel<4, 4>), gr, bl, lds, 0, a, pos, mode, P, memf);
-    else hipLaunchKernelGGL((build_prune_kernel<16, 1>), gr, bl, lds, 0, a, pos, mode, P, memf);
+    launch_prune_kind<false>(a, dim3((unsigned)grid), (size_t)prune_wave_bytes(P, memf), pos, mode, P, memf,
+                             nullptr, 0);
     return hipGetLastError();
+}
+
+// The global-memory pass over the same blocks for the nbig larger prunes of
+// up to Pbig candidates; the scratch buffer grows to hold them.
+jag_status launch_prune_big(const BArgs &a, DevBufs &B, unsigned char *&gs, size_t &gs_bytes, int32_t grid,
+                            int64_t pos, int32_t mode, int32_t Pbig, int32_t nbig)
+{
+    const int64_t gbytes = ((int64_t)prune_wave_bytes(Pbig, 0) + 255) / 256 * 256;
+    const size_t need = (size_t)gbytes * (size_t)nbig;
+    if (need > gs_bytes) {
+        unsigned char *p = nullptr;
+        HIP_OK(B.alloc(&p, need));
+        gs = p;  // the smaller buffer stays with B until the build ends
+        gs_bytes = need;
+    }
+    HIP_OK(hipMemset(a.ctr + 5, 0, 4));
+    launch_prune_kind<true>(a, dim3((unsigned)grid), 0, pos, mode, Pbig, 0, gs, gbytes);
+    HIP_OK(hipGetLastError());
+    return JAG_OK;
 }
 
 int pow2_at_least(int x)
@@ -833,7 +910,9 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
     HIP_OK(hipMemset(dfill, 0, (size_t)n * 4));
     HIP_OK(B.alloc(&dtouch, (size_t)maxnb * R));
     HIP_OK(B.alloc(&dinl, (size_t)maxnb * R));
-    HIP_OK(B.alloc(&dctr, 4));
+    HIP_OK(B.alloc(&dctr, 8));
+    unsigned char *gscratch = nullptr;  // global-memory prunes, grown on demand
+    size_t gscratch_bytes = 0;
 
     a.X = dX;
     a.n = n;
@@ -869,20 +948,24 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
     while (pos < n) {
         const int64_t be = std::min<int64_t>(n, pos + bs);
         const int32_t nb = (int32_t)(be - pos);
-        int32_t hctr[4];
-        HIP_OK(hipMemset(dctr, 0, 16));
+        int32_t hctr[8];
+        HIP_OK(hipMemset(dctr, 0, 32));
         HIP_OK(hipMemset(dptot, 0, (size_t)nb * 8));
         const int64_t waves = (int64_t)nb * nT;
         hipLaunchKernelGGL(build_search_kernel, dim3((unsigned)((waves + kSW - 1) / kSW)), dim3(64 * kSW),
                            search_lds, 0, a, pos, nb);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpy(hctr, dctr, 16, hipMemcpyDeviceToHost));
-        if (hctr[3] > kMaxCand) {
-            set_error("an insertion expanded %d vertices in all; the device builder holds %d", hctr[3], kMaxCand);
+        HIP_OK(hipMemcpy(hctr, dctr, 32, hipMemcpyDeviceToHost));
+        if (hctr[3] > kMaxBigCand) {
+            set_error("an insertion expanded %d vertices in all; the device builder holds %d", hctr[3], kMaxBigCand);
             return JAG_EUNSUPPORTED;
         }
-        const int P1 = pow2_at_least(hctr[3]);
-        HIP_OK(launch_prune(a, nb, pos, 0, P1));
+        HIP_OK(launch_prune(a, nb, pos, 0, pow2_at_least(std::min(hctr[3], kMaxCand))));
+        if (hctr[4] > 0) {
+            jag_status st = launch_prune_big(a, B, gscratch, gscratch_bytes, nb, pos, 0, pow2_at_least(hctr[3]),
+                                             hctr[4]);
+            if (st != JAG_OK) return st;
+        }
         const unsigned eb = (unsigned)(((int64_t)nb * R + 255) / 256);
         hipLaunchKernelGGL(rev_count_kernel, dim3(eb), dim3(256), 0, 0, a, pos, nb);
         HIP_OK(hipGetLastError());
@@ -890,15 +973,19 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
         HIP_OK(hipGetLastError());
         hipLaunchKernelGGL(rev_fill_kernel, dim3(eb), dim3(256), 0, 0, a, pos, nb);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipMemcpy(hctr, dctr, 16, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(hctr, dctr, 32, hipMemcpyDeviceToHost));
         if (hctr[0] > 0) {
-            if (hctr[2] + R > kMaxCand) {
+            if (hctr[2] + R > kMaxBigCand) {
                 set_error("a vertex gained %d in-links in one round; the device builder holds %d (lower max_batch)",
-                          hctr[2], kMaxCand - R);
+                          hctr[2], kMaxBigCand - R);
                 return JAG_EUNSUPPORTED;
             }
-            const int P2 = pow2_at_least(hctr[2] + R);
-            HIP_OK(launch_prune(a, hctr[0], pos, 1, P2));
+            HIP_OK(launch_prune(a, hctr[0], pos, 1, pow2_at_least(std::min(hctr[2] + R, kMaxCand))));
+            if (hctr[6] > 0) {
+                jag_status st = launch_prune_big(a, B, gscratch, gscratch_bytes, hctr[0], pos, 1,
+                                                 pow2_at_least(hctr[2] + R), hctr[6]);
+                if (st != JAG_OK) return st;
+            }
         }
         if (cfg.progress && (pos * 10) / n != (be * 10) / n) {
             HIP_OK(hipDeviceSynchronize());

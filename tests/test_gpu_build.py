@@ -141,16 +141,21 @@ def test_device_build_smallest_and_largest_dimension(d):
     assert de == he and np.array_equal(dadj, hadj)
 
 
-def test_device_build_reports_a_round_too_large_for_its_buffers():
-    """Identical points all link to the same vertex; a round of 8,192 of them
-    gives it more in-links than one prune holds, which the host reports."""
+def test_device_build_hub_vertices_take_the_global_memory_prune():
+    """Identical points all link to the same vertex: a round of 8,192 of them
+    gives it more in-links than one LDS prune holds, so its prune runs with
+    its arrays in global memory; the graph still equals the host builder's."""
     X = np.zeros((20000, 8), np.float32)
     scal = np.zeros(20000, np.int32)
-    _say("device build of 20,000 identical points, one round of 8,192")
-    with pytest.raises(jag.JagError, match="in-links"):
-        jag.jag_build_graph(X, scalar=scal, R=8, thresholds=[(S, 1.0)], max_batch=20000, device=True)
-    # rounds small enough stay within the buffers
-    adj, e = jag.jag_build_graph(X[:3000], scalar=scal[:3000], R=8, thresholds=[(S, 1.0)], max_batch=1000,
-                                 device=True)
-    hadj, he = jag.jag_build_graph(X[:3000], scalar=scal[:3000], R=8, thresholds=[(S, 1.0)], max_batch=1000)
-    assert e == he and np.array_equal(adj, hadj)
+    kw = dict(scalar=scal, R=8, thresholds=[(S, 1.0), (S, 0.0)], max_batch=20000)
+    _say("device build of 20,000 identical points, rounds up to 8,192")
+    dadj, de = jag.jag_build_graph(X, device=True, **kw)
+    hadj, he = jag.jag_build_graph(X, **kw)
+    assert de == he and np.array_equal(dadj, hadj)
+    # and the same at a degree above 64 with mixed rows
+    X2, s2, lo2, la2 = small_world(6000, 16, seed=3)
+    X2[:3000] = X2[0]
+    kw2 = dict(scalar=s2, R=96, thresholds=[(S, 1.0), (S, 0.0)], max_batch=6000)
+    dadj, de = jag.jag_build_graph(X2, device=True, **kw2)
+    hadj, he = jag.jag_build_graph(X2, **kw2)
+    assert de == he and np.array_equal(dadj, hadj)
