@@ -217,6 +217,8 @@ def serve_main(args):
 
     n = args.n or 1_250_000
     w = make_config("c5", n=n, nq=args.nq or 10000)
+    if args.R:
+        w = dataclasses.replace(w, R=args.R)
     k = w.k
     log(f"serving workload c5 shard: n={w.n} d={w.d} nq={w.nq}")
     t1 = time.time()
