@@ -21,6 +21,11 @@
 //                        plus its new in-links in id order, pruned again with
 //                        its own thresholds when that exceeds R.
 //
+// A prune keeps its candidates in LDS when they number at most kMaxCand;
+// the rare larger ones (a hub vertex gaining thousands of in-links in one
+// round) run in a second launch with their arrays in global scratch.  Rows
+// of more than 64 neighbours are read in slices of 64.
+//
 // The new points of a round cannot be reached from the graph before the
 // round (nothing links to them yet), so their out-rows are written in place.
 #include <hip/hip_runtime.h>
@@ -197,7 +202,7 @@ __device__ __forceinline__ void wsync()
 // Bytes of LDS one search wave uses.
 __host__ __device__ constexpr int search_wave_bytes(int d4)
 {
-    return kMaxLb * 8 + kMaxLb * 4 + kSeenSlots * 4 + 64 * (8 + 4 + 4 + 4 + 4 + 4 + 4) + d4 * 4;
+    return kMaxLb * 8 + kMaxLb * 4 + kSeenSlots * 4 + 64 * (8 + 4 + 4 + 4 + 4 + 4) + d4 * 4;
 }
 
 // GreedySearch(G, x_p, 1, l_b, D_A^t) of Algorithm 3: the beam holds the l_b
@@ -223,8 +228,7 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
     float *cf = reinterpret_cast<float *>(cu + 64);
     float *cd2 = cf + 64;
     int32_t *cid = reinterpret_cast<int32_t *>(cd2 + 64);
-    int32_t *cpos = cid + 64;
-    int32_t *spos = cpos + 64;
+    int32_t *spos = cid + 64;
     float *xp = reinterpret_cast<float *>(spos + 64);
 
     for (int i = lane; i < kSeenSlots; i += 64) seen[i] = -1;
