@@ -54,7 +54,7 @@ constexpr uint32_t kIdMask = 0x7FFFFFFFu;
         hipError_t e_ = (x);                                                        \
         if (e_ != hipSuccess) {                                                     \
             set_error("%s failed: %s", #x, hipGetErrorString(e_));                  \
-            return JAG_EDEVICE;                                                     \
+            return e_ == hipErrorOutOfMemory ? JAG_ENOMEM : JAG_EDEVICE;            \
         }                                                                           \
     } while (0)
 
