@@ -173,17 +173,19 @@ typedef struct {
                             (occupancy) against repeated evaluations; results do not
                             depend on it. */
     int32_t single_pass; /* learned == 1 only.  0 = two launches: the first runs every
-                            query to its prediction point and records its beam, the
-                            second searches from the start with the queries in order of
-                            decreasing predicted beam (longest first, so the batch
-                            does not end on a few long searches), reusing the recorded
-                            beams; 1 = one launch in submission order.  Results are
-                            identical.  Two passes allocate stream-ordered device
-                            scratch (hipMallocAsync on the call's stream) for each
-                            query's saved state: (8 + 3*W + S + 2) * 4 bytes, W = list
-                            width (64 or the widest beam, rounded up to 64), S =
-                            seen-table slots (4.9 KB at W = 64, S = 1024); batches
-                            needing more than 512 MiB run in chunks. */
+                            query to its prediction point and saves its list and
+                            counters; the second resumes the saved searches in order
+                            of decreasing predicted beam (longest first, so the batch
+                            does not end on a few long searches); 1 = one launch in
+                            submission order.  Ids, distances, counts, expansions and
+                            beams are identical; the distance and attribute counts of
+                            stats may differ, since a resumed search starts its
+                            seen-table again from its list.  Two passes allocate
+                            stream-ordered device scratch (hipMallocAsync on the call's
+                            stream) for each query's saved state: (8 + 3*W + 2) * 4
+                            bytes, W = list width (64 or the widest beam, rounded up
+                            to 64; 0.8 KB at W = 64); batches needing more than
+                            512 MiB run in chunks. */
 } jag_search_params;
 
 typedef struct {

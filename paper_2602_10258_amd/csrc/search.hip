@@ -605,12 +605,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         predicted = true;
         const uint64_t *sk = reinterpret_cast<const uint64_t *>(rs + 8);
         const uint32_t *si = reinterpret_cast<const uint32_t *>(rs + 8 + 2 * a.Lcap);
-        const int4 *sh = reinterpret_cast<const int4 *>(rs + 8 + 3 * a.Lcap);
         for (int j = lane; j < cnt; j += 64) {
             s.key[j] = sk[j];
             s.idf[j] = si[j];
         }
-        for (int j = lane; j < (H >> 2); j += 64) reinterpret_cast<int4 *>(s.hash)[j] = sh[j];
+        // the seen-table starts again from the list's ids: a forgotten vertex
+        // is recognised at the merge or cannot re-enter (I1), so the results
+        // are those of the one-pass search; a table that holds only the list
+        // also forgets less later on than the full one would
+        for (int i = lane; i < H; i += 64) s.hash[i] = -1;
+        __syncthreads();
+        for (int j = lane; j < cnt; j += 64) hash_insert(s.hash, a.Hmask, (int32_t)(si[j] & kIdMask));
         __syncthreads();
     } else {
         for (int i = lane; i < H; i += 64) s.hash[i] = -1;
@@ -726,12 +731,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     int32_t *ws = a.state + q * a.state_stride;
                     uint64_t *sk = reinterpret_cast<uint64_t *>(ws + 8);
                     uint32_t *si = reinterpret_cast<uint32_t *>(ws + 8 + 2 * a.Lcap);
-                    int4 *sh = reinterpret_cast<int4 *>(ws + 8 + 3 * a.Lcap);
                     for (int j = lane; j < cnt; j += 64) {
                         sk[j] = s.key[j];
                         si[j] = s.idf[j];
                     }
-                    for (int j = lane; j < (H >> 2); j += 64) sh[j] = reinterpret_cast<const int4 *>(s.hash)[j];
                     if (lane < 8) {
                         int v = lane == 0 ? idx + 1 : lane == 1 ? cnt : lane == 2 ? hint : lane == 3 ? hops
                               : lane == 4 ? ndist : lane == 5 ? nattr : lane == 6 ? hopcap : lhat;
@@ -1079,9 +1082,9 @@ constexpr int kWarmWidth = 64;
 // batches are processed in chunks of queries that fit.
 constexpr int64_t kStateBudget = int64_t(512) << 20;
 
-// Words of one saved search state: 8 counters, the list (8-byte keys and
-// 4-byte ids of up to Lcap entries) and the H-slot seen-table.
-constexpr int64_t state_words(int Lcap, int H) { return 8 + 3 * (int64_t)Lcap + H; }
+// Words of one saved search state: 8 counters and the list (8-byte keys and
+// 4-byte ids of up to Lcap entries).
+constexpr int64_t state_words(int Lcap) { return 8 + 3 * (int64_t)Lcap; }
 
 }  // namespace
 
@@ -1372,7 +1375,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         return JAG_OK;
     }
     // two passes over chunks of queries: run each to its prediction and save
-    // its state (list, seen-table, counters), order the chunk by predicted
+    // its state (list and counters), order the chunk by predicted
     // beam, widest first, then resume every search in that order.  The
     // scratch comes from the device's default memory pool, which is told to
     // keep freed memory reserved so that repeated searches do not return it
@@ -1384,7 +1387,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
         }
     }
-    const int64_t stride = state_words(a.Lcap, a.Hmask + 1);
+    const int64_t stride = state_words(a.Lcap);
     const int64_t per_q = (stride + 2) * (int64_t)sizeof(int32_t);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
     int32_t *scratch = nullptr;
@@ -1457,7 +1460,7 @@ jag_status search_scratch_bytes(Index &ix, int32_t k, const jag_search_params &S
     if (st != JAG_OK) return st;
     *bytes = 0;
     if (S.learned == 1 && !S.single_pass && nq >= 2) {
-        const int64_t per_q = (state_words(a.Lcap, a.Hmask + 1) + 2) * (int64_t)sizeof(int32_t);
+        const int64_t per_q = (state_words(a.Lcap) + 2) * (int64_t)sizeof(int32_t);
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
         *bytes = chunk * per_q;
     }

@@ -123,8 +123,9 @@ def test_learned_cut_is_exact(c1_small):
 def test_two_pass_schedule_is_exact(c1_small, mixed_world):
     """The default two-pass learned search (run to the prediction and save the
     state, order longest first, resume) returns exactly what one launch in
-    submission order returns: ids, distances, counts, expansions, distance
-    and attribute counts, chosen beams."""
+    submission order returns: ids, distances, counts, expansions and chosen
+    beams.  (The distance and attribute counts may differ: the resumed search
+    starts its seen-table again from its list, which I1 makes harmless.)"""
     w, A, adj, entry = c1_small
     _say("two-pass learned schedule")
     ladder = np.array([10, 16, 24, 40, 64, 96, 128], dtype=np.int32)
@@ -146,8 +147,9 @@ def test_two_pass_schedule_is_exact(c1_small, mixed_world):
                              max_hops=mh)
             two = gpu_search(ix, Q, F, pool, 10, 10, learned=1, delta=delta, single_pass=0,
                              max_hops=mh)
-            for key in ("ids", "d2", "count", "stats"):
+            for key in ("ids", "d2", "count"):
                 assert np.array_equal(one[key], two[key]), (seed, delta, key)
+            assert np.array_equal(one["stats"][:, [0, 3]], two["stats"][:, [0, 3]]), (seed, delta)
         _say(f"case {seed}: beams {np.unique(two['stats'][:, 3]).tolist()}")
 
 
