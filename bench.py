@@ -499,7 +499,7 @@ def main():
         log(f"predictor fitted on {fit_rep.n_train} traces in {time.time() - t3:.1f}s: loss "
             f"{fit_rep.loss_first:.3f} -> {fit_rep.loss_last:.3f}, rho={rho:.2f}, "
             f"unreachable={fit_rep.unreachable}")
-        for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0]:
+        for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0]:
             r = point(ix16, rec16, jag.SearchParams(L=k, learned=1, delta=delta, rerank_mult=4))
             r["delta"] = delta
             learned.append(r)
