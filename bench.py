@@ -607,7 +607,8 @@ def main():
         per_q = per_q + 4 * k * 4 * w.d
     alg_bytes = float(per_q.sum())
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
-    op_name = f"{op['mode']} L={op['sp'].L}" if not op["sp"].learned else op["mode"]
+    op_name = (f"{op['mode']} L={op['sp'].L}" if not op["sp"].learned
+               else f"{op['mode']} delta={op['sp'].delta:g}")
     traffic = measured_traffic(w.name, op_name)
 
     # ---- CPU baseline: the oracle, unchanged, on a bounded sample at the same beam
