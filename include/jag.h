@@ -215,7 +215,10 @@ typedef struct {
  * thresholds; L_build > 256 on the device), ENOMEM, EDEVICE, EUNSUPPORTED
  * (device rounds only: one insertion expanding more than 65536 vertices over
  * all its searches, or a vertex gaining more than 65536 - R in-links in one
- * round; a smaller max_batch avoids the latter).
+ * round; a smaller max_batch avoids the latter).  A prune of more than 4096
+ * candidates runs with its arrays in device memory instead of LDS, with the
+ * same result; the environment variable JAG_BUILD_LDS_CANDIDATES (64..4096)
+ * lowers that limit, which only serves to exercise that path in tests.
  */
 jag_status jag_build(const float *X, int64_t n, int32_t d, const jag_attrs *A,
                      const jag_build_params *P, jag_index **out);

@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "jag_internal.h"
@@ -83,7 +84,8 @@ struct BArgs {
     int32_t *touched;      // [maxnb * R]
     int32_t *inl;          // [maxnb * R]
     int32_t *ctr;          // [0] targets, [1] in-link cursor, [2] largest in-count, [3] largest union,
-                           // [4] insertions and [6] targets above kMaxCand candidates, [5] scratch slots
+                           // [4] insertions and [6] targets above lds_cap candidates, [5] scratch slots
+    int32_t lds_cap;       // largest candidate set a prune keeps in LDS (kMaxCand)
 };
 
 __device__ __forceinline__ bool key_less(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib)
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(256) void build_search_kernel(BArgs a, int64_t pos0
         if ((int)(old >> 32) == a.nT - 1) {
             const int32_t total = (int32_t)(old & 0xFFFFFFFFull) + hops;
             atomicMax(&a.ctr[3], total);
-            if (total > kMaxCand) atomicAdd(&a.ctr[4], 1);  // prunes for the global-memory pass
+            if (total > a.lds_cap) atomicAdd(&a.ctr[4], 1);  // prunes for the global-memory pass
         }
     }
 }
@@ -624,7 +626,7 @@ __device__ void prune_core(const BArgs &a, int64_t v, int32_t *V, int nv, float 
 
 // Mode 0: prune the union of a new point's expanded sets into its row.
 // Mode 1: merge a target's new in-links into its row (re-pruned above R).
-// GM = false: prunes of at most kMaxCand candidates, arrays in LDS (P slots,
+// GM = false: prunes of at most lds_cap candidates, arrays in LDS (P slots,
 // memf floats of member rows); blocks with larger candidate sets return at
 // once.  GM = true: only those larger prunes, each with P slots in its own
 // gbytes of global scratch (slots handed out by ctr[5]) and member rows read
@@ -639,9 +641,9 @@ __global__ __launch_bounds__(64) void build_prune_kernel(BArgs a, int64_t pos0, 
     if (mode == 0) {
         int tot = 0;
         for (int ti = 0; ti < a.nT; ti++) tot += a.expcnt[(int64_t)blockIdx.x * a.nT + ti];
-        big = tot > kMaxCand;
+        big = tot > a.lds_cap;
     } else {
-        big = a.incnt[a.touched[blockIdx.x]] + a.R > kMaxCand;
+        big = a.incnt[a.touched[blockIdx.x]] + a.R > a.lds_cap;
     }
     if (big != GM) return;
     unsigned char *base = smem;
@@ -758,7 +760,7 @@ __global__ void rev_offset_kernel(BArgs a)
     base = __shfl(base, 63);
     if (t < nt) a.segoff[a.touched[t]] = base + incl - c;
     if (lane == 0) atomicMax(&a.ctr[2], mx);
-    const uint64_t big = __ballot(t < nt && c + a.R > kMaxCand);  // prunes for the global-memory pass
+    const uint64_t big = __ballot(t < nt && c + a.R > a.lds_cap);  // prunes for the global-memory pass
     if (lane == 0 && big) atomicAdd(&a.ctr[6], (int)__popcll(big));
 }
 
@@ -808,7 +810,7 @@ void launch_prune_kind(const BArgs &a, dim3 gr, size_t lds, int64_t pos, int32_t
         hipLaunchKernelGGL((build_prune_kernel<16, 1, GM>), gr, bl, lds, 0, a, pos, mode, P, memf, gs, gbytes);
 }
 
-// The LDS pass over all blocks (prunes of up to kMaxCand candidates, P slots;
+// The LDS pass over all blocks (prunes of up to lds_cap candidates, P slots;
 // member rows go to LDS when the wave's LDS stays within 64 KB).
 hipError_t launch_prune(const BArgs &a, int32_t grid, int64_t pos, int32_t mode, int32_t P)
 {
@@ -946,6 +948,13 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
     a.touched = dtouch;
     a.inl = dinl;
     a.ctr = dctr;
+    // JAG_BUILD_LDS_CANDIDATES (64..4096) lowers the LDS capacity of a prune,
+    // which sends more prunes through the global-memory pass (for testing it)
+    a.lds_cap = kMaxCand;
+    if (const char *e = std::getenv("JAG_BUILD_LDS_CANDIDATES")) {
+        const int v = std::atoi(e);
+        if (v >= 64 && v <= kMaxCand) a.lds_cap = v;
+    }
 
     const int search_lds = kSW * search_wave_bytes(d4);
     int64_t pos = 1, bs = 1;
@@ -964,7 +973,7 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
             set_error("an insertion expanded %d vertices in all; the device builder holds %d", hctr[3], kMaxBigCand);
             return JAG_EUNSUPPORTED;
         }
-        HIP_OK(launch_prune(a, nb, pos, 0, pow2_at_least(std::min(hctr[3], kMaxCand))));
+        HIP_OK(launch_prune(a, nb, pos, 0, pow2_at_least(std::min(hctr[3], a.lds_cap))));
         if (hctr[4] > 0) {
             jag_status st = launch_prune_big(a, B, gscratch, gscratch_bytes, nb, pos, 0, pow2_at_least(hctr[3]),
                                              hctr[4]);
@@ -984,7 +993,7 @@ jag_status build_graph_device(const float *X, int64_t n, int32_t d, const AttrVi
                           hctr[2], kMaxBigCand - R);
                 return JAG_EUNSUPPORTED;
             }
-            HIP_OK(launch_prune(a, hctr[0], pos, 1, pow2_at_least(std::min(hctr[2] + R, kMaxCand))));
+            HIP_OK(launch_prune(a, hctr[0], pos, 1, pow2_at_least(std::min(hctr[2] + R, a.lds_cap))));
             if (hctr[6] > 0) {
                 jag_status st = launch_prune_big(a, B, gscratch, gscratch_bytes, hctr[0], pos, 1,
                                                  pow2_at_least(hctr[2] + R), hctr[6]);

@@ -159,3 +159,17 @@ def test_device_build_hub_vertices_take_the_global_memory_prune():
     dadj, de = jag.jag_build_graph(X2, device=True, **kw2)
     hadj, he = jag.jag_build_graph(X2, **kw2)
     assert de == he and np.array_equal(dadj, hadj)
+
+
+@pytest.mark.parametrize("cap", ["64", "256"])
+def test_device_build_global_memory_prunes_for_insertions_and_reverse_edges(monkeypatch, cap):
+    """With the LDS capacity of a prune lowered (JAG_BUILD_LDS_CANDIDATES),
+    insertion prunes and reverse-edge prunes go through the global-memory
+    pass (all of them at 64, some at 256); the graph is still the host's."""
+    w = make_config("c2", n=20000, nq=10)
+    kw = dict(scalar=w.scalar, R=64, thresholds=[(S, 1.0), (S, 0.01), (S, 0.0)], seed=5)
+    hadj, he = jag.jag_build_graph(w.X, **kw)
+    monkeypatch.setenv("JAG_BUILD_LDS_CANDIDATES", cap)
+    _say("device build with prunes of more than", cap, "candidates in global memory")
+    dadj, de = jag.jag_build_graph(w.X, device=True, **kw)
+    assert de == he and np.array_equal(dadj, hadj)
