@@ -509,8 +509,10 @@ def main():
                 break
 
     def at95(curve):
+        # the first sweep point (smallest beam or offset) at or above 0.95:
+        # deterministic, where the fastest of several such points is noise
         ok = [r for r in curve if r["recall"] >= 0.95]
-        best = max(ok, key=lambda r: r["qps"]) if ok else None
+        best = ok[0] if ok else None
         interp = None
         srt = sorted(curve, key=lambda r: r["recall"])
         for a, b in zip(srt, srt[1:]):
