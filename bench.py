@@ -5,15 +5,16 @@ vectors, d = 96, 256-cluster Gaussian mixture, one int32 attribute uniform
 over [0, 10^6); 10,000 range queries with log-uniform selectivity over
 [1e-4, 1]; k = 10; graph R = 64, thresholds {100%, 1%, 0} of the scalar.
 
-Setup (untimed): build the Threshold-JAG on host threads, lay out an FP32
-index and a BF16 index (with FP32 copy) over the same graph, compute the
-exact answers with the CPU oracle (FP64), sweep the fixed beam L for plain
-FP32 search, fit the beam predictor on a separate query set (GPU kernels),
-sweep its offset for learned + BF16 + FP32-rerank search.  The timed steps
-then run the fastest configuration that reaches recall >= 0.95 over the
-whole query batch, inputs resident in HBM.  One JSON line on stdout.
+Setup (untimed): build the Threshold-JAG (on the GPU by default; --build
+host or both), lay out FP32, BF16 and FP8 indexes (with FP32 copies) over
+the same graph, compute the exact answers with the CPU oracle (FP64), sweep
+the fixed beam L for each store, fit the beam predictor on a separate query
+set (GPU kernels), sweep its offset for learned + BF16 + FP32-rerank search.
+Each mode's point is the first sweep point reaching recall >= 0.95; the
+timed steps run the fastest of those over the whole query batch, inputs
+resident in HBM.  One JSON line on stdout.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config c2|c1|c3]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config c2|c1|c3|c5|bool15]
 """
 from __future__ import annotations
 
