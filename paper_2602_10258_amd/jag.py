@@ -74,6 +74,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2602_10258_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 under
+        # the same soname.  Loaded first, it is the one libjag binds to;
+        # loaded after libjag, a second HIP and HSA runtime would be mapped
+        # beside the system's and PyTorch would find no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P, i32, i64, f32, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_uint64
         sig = {

@@ -30,6 +30,22 @@ def test_library_exports_every_header_symbol():
     assert b"gfx950" in L.jag_version()
 
 
+def test_library_shares_one_hip_runtime_with_torch():
+    """Loading the library before anything imports torch must not map a second
+    HIP runtime beside PyTorch's (with two, PyTorch finds no device)."""
+    import subprocess
+    import sys
+    code = ("import os, sys; sys.path.insert(0, %r)\n"
+            "from paper_2602_10258_amd import jag\n"
+            "jag.lib()\n"
+            "import torch\n"
+            "m = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(m), sorted(m))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split()[0] == "1", out.stdout
+
+
 def test_build_graph_rejects_bad_arguments():
     X = np.zeros((10, 4), np.float32)
     with pytest.raises(jag.JagError) as e:
