@@ -176,8 +176,9 @@ typedef struct {
                             query to its prediction point and saves its list and
                             counters; the second resumes the saved searches in order
                             of decreasing predicted beam (longest first, so the batch
-                            does not end on a few long searches); 1 = one launch in
-                            submission order.  Ids, distances, counts, expansions and
+                            does not end on a few long searches); 1 = one launch
+                            (ordered as a fixed-beam launch is, below).  Ids,
+                            distances, counts, expansions and
                             beams are identical; the distance and attribute counts of
                             stats may differ, since a resumed search starts its
                             seen-table again from its list.  Two passes allocate
@@ -304,7 +305,12 @@ jag_status jag_encode_filters_sized(const jag_index *idx, const jag_filter *F, i
  * dists[nq][k] the matching squared distances (from the FP32 copy when
  * reranking, else from the store; +inf for padding); count[nq] the number
  * of valid ids.  Asynchronous on `stream` (a hipStream_t; NULL = default
- * stream).  Errors: EINVAL (k < 1, k > 64, L < k, L > 1024, bad params),
+ * stream).  Launch order: a batch of at least 4096 queries at a fixed
+ * beam (or learned with single_pass = 1) runs broadest filter first, by
+ * classes of the records' selectivity estimate, so that the batch does not
+ * end on a few long searches; it takes nq * 8 bytes of stream-ordered
+ * device scratch for the order.  No result depends on the order.
+ * Errors: EINVAL (k < 1, k > 64, L < k, L > 1024, bad params),
  * EUNSUPPORTED (rerank without an FP32 copy, learned without predictor),
  * EDEVICE.
  */

@@ -930,26 +930,66 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
 }
 
 // ---------------------------------------------------------------- schedule
-// Longest-predicted-first order for the search pass of a two-pass learned
-// search: a counting sort of the queries by key = 1 + predicted ladder index
-// (0 = finished before the prediction point), largest first.  One workgroup;
-// thread t owns queries t, t + 512, t + 1024, ... (coalesced key reads);
-// within a class the order is (thread, then position), not the query order,
-// which no result depends on.
+// Longest-first orders for a launch, by a counting sort over 17 classes,
+// largest class first.  Two-pass learned search: class = 1 + predicted
+// ladder index (0 = finished before the prediction point).  One launch of
+// many queries at a fixed beam, or one-pass learned: class = the filter's
+// log2 selectivity estimate in steps of about two octaves, broadest first (on
+// the range workload the log estimate correlates +0.55 with a query's
+// expansions, so the broad filters run first and the launch does not end on
+// them); class_kernel, one thread per query, first copies these classes
+// out of the 128-byte records, so that the sort reads 4 bytes per query
+// (one compute unit reading every record line itself takes 35 us at 10,000
+// queries).  The sort is one workgroup; thread t owns queries t, t + 512,
+// t + 1024, ... (coalesced reads), taken 16 at a time so that 16
+// independent loads are in flight per thread; within a class the order is
+// (thread, then position), not the query order, which no result depends on.
 constexpr int kOrderThreads = 512;
+constexpr int kOrderBatch = 16;
 constexpr int kOrderBins = JAG_LADDER_MAX + 1;
+// Fixed-beam and one-pass learned launches of at least this many queries
+// are ordered by selectivity (smaller ones fit on the device at once, where
+// the order hardly matters).
+constexpr int64_t kSelOrderMin = 4096;
 
+static bool sel_ordered(const jag_search_params &S, int64_t nq)
+{
+    return (S.learned == 0 || (S.learned == 1 && S.single_pass)) && nq >= kSelOrderMin;
+}
+
+__global__ __launch_bounds__(256) void class_kernel(const FilterRecord *rec, int64_t nq, int32_t *key)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nq) return;
+    const float x = rec[i].sel_feature;  // log2(selectivity) / 16, in [-1.9, 0]
+    const float c = floorf(16.f + x * (256.f / 30.f));
+    key[i] = c >= 0.f ? (int)c : 0;
+}
+
+__device__ __forceinline__ int order_class(const int32_t *key, int64_t i)
+{
+    const int k = key[i];
+    return k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
+}
+
+// Both loops clamp the index instead of branching on it, so that the
+// batch's loads issue back to back.
 __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key, int64_t nq, int32_t *perm)
 {
     __shared__ int32_t cnt[kOrderBins][kOrderThreads];
     __shared__ int32_t part[kOrderThreads];
     const int t = threadIdx.x;
     for (int b = 0; b < kOrderBins; b++) cnt[b][t] = 0;
-#pragma unroll 4
-    for (int64_t i = t; i < nq; i += kOrderThreads) {
-        int k = key[i];
-        k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
-        cnt[k][t]++;
+    for (int64_t i0 = t; i0 < nq; i0 += (int64_t)kOrderThreads * kOrderBatch) {
+        int c[kOrderBatch];
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; j++) {
+            const int64_t i = i0 + (int64_t)j * kOrderThreads;
+            c[j] = order_class(key, i < nq ? i : nq - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; j++)
+            if (i0 + (int64_t)j * kOrderThreads < nq) cnt[c[j]][t]++;
     }
     __syncthreads();
     // output rank r enumerates (bin descending, thread ascending); thread t
@@ -977,11 +1017,30 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key
         run += v;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int64_t i = t; i < nq; i += kOrderThreads) {
-        int k = key[i];
-        k = k < 0 ? 0 : (k >= kOrderBins ? kOrderBins - 1 : k);
-        perm[cnt[k][t]++] = (int32_t)i;
+    for (int64_t i0 = t; i0 < nq; i0 += (int64_t)kOrderThreads * kOrderBatch) {
+        int c[kOrderBatch];
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; j++) {
+            const int64_t i = i0 + (int64_t)j * kOrderThreads;
+            c[j] = order_class(key, i < nq ? i : nq - 1);
+        }
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; j++) {
+            const int64_t i = i0 + (int64_t)j * kOrderThreads;
+            if (i < nq) perm[cnt[c[j]][t]++] = (int32_t)i;
+        }
+    }
+}
+
+// The device's default memory pool keeps freed memory reserved, so that the
+// stream-ordered scratch of repeated searches is not returned to the system
+// and allocated again.
+static void keep_pool_reserved(int device)
+{
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
     }
 }
 
@@ -1369,6 +1428,29 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     if (st != JAG_OK) return st;
     if (nq == 0) return JAG_OK;
     hipStream_t sm = (hipStream_t)stream;
+    if (sel_ordered(S, nq)) {
+        // one launch, broadest filters first
+        keep_pool_reserved(ix.device);
+        int32_t *perm = nullptr;
+        HIPCHK(hipMallocAsync((void **)&perm, 2 * sizeof(int32_t) * (size_t)nq, sm));
+        int32_t *key = perm + nq;
+        hipLaunchKernelGGL(class_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, sm, a.rec, nq, key);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, key, nq, perm);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            SearchArgs b = a;
+            b.perm = perm;
+            hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, sm, b);
+            e = hipGetLastError();
+        }
+        hipError_t ef = hipFreeAsync(perm, sm);
+        HIPCHK(e);
+        HIPCHK(ef);
+        return JAG_OK;
+    }
     if (S.learned != 1 || S.single_pass || nq < 2) {
         hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, sm, a);
         HIPCHK(hipGetLastError());
@@ -1376,17 +1458,9 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     }
     // two passes over chunks of queries: run each to its prediction and save
     // its state (list and counters), order the chunk by predicted
-    // beam, widest first, then resume every search in that order.  The
-    // scratch comes from the device's default memory pool, which is told to
-    // keep freed memory reserved so that repeated searches do not return it
-    // to the system and allocate it again.
-    {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, ix.device) == hipSuccess) {
-            uint64_t keep = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        }
-    }
+    // beam, widest first, then resume every search in that order; the
+    // scratch is stream-ordered memory from the default pool
+    keep_pool_reserved(ix.device);
     const int64_t stride = state_words(a.Lcap);
     const int64_t per_q = (stride + 2) * (int64_t)sizeof(int32_t);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
@@ -1463,6 +1537,8 @@ jag_status search_scratch_bytes(Index &ix, int32_t k, const jag_search_params &S
         const int64_t per_q = (state_words(a.Lcap) + 2) * (int64_t)sizeof(int32_t);
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
         *bytes = chunk * per_q;
+    } else if (sel_ordered(S, nq)) {
+        *bytes = 2 * nq * (int64_t)sizeof(int32_t);  // the launch order and the classes
     }
     return JAG_OK;
 }
