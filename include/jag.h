@@ -306,10 +306,12 @@ jag_status jag_encode_filters_sized(const jag_index *idx, const jag_filter *F, i
  * reranking, else from the store; +inf for padding); count[nq] the number
  * of valid ids.  Asynchronous on `stream` (a hipStream_t; NULL = default
  * stream).  Launch order: a batch of at least 4096 queries at a fixed
- * beam (or learned with single_pass = 1) runs broadest filter first, by
- * classes of the records' selectivity estimate, so that the batch does not
- * end on a few long searches; it takes nq * 8 bytes of stream-ordered
- * device scratch for the order.  No result depends on the order.
+ * beam (or learned with single_pass = 1) runs the searches expected to be
+ * long first, by classes of the records' selectivity estimate (range
+ * filters broadest first, label-based filters narrowest first), so that
+ * the batch does not end on a few long searches; it takes nq * 8 bytes of
+ * stream-ordered device scratch for the order.  No result depends on the
+ * order.
  * Errors: EINVAL (k < 1, k > 64, L < k, L > 1024, bad params),
  * EUNSUPPORTED (rerank without an FP32 copy, learned without predictor),
  * EDEVICE.

@@ -934,13 +934,16 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
 // largest class first.  Two-pass learned search: class = 1 + predicted
 // ladder index (0 = finished before the prediction point).  One launch of
 // many queries at a fixed beam, or one-pass learned: class = the filter's
-// log2 selectivity estimate in steps of about two octaves, broadest first (on
-// the range workload the log estimate correlates +0.55 with a query's
-// expansions, so the broad filters run first and the launch does not end on
-// them); class_kernel, one thread per query, first copies these classes
-// out of the 128-byte records, so that the sort reads 4 bytes per query
-// (one compute unit reading every record line itself takes 35 us at 10,000
-// queries).  The sort is one workgroup; thread t owns queries t, t + 512,
+// log2 selectivity estimate in steps of about two octaves, ranked so that
+// the searches expected to be long run first and the launch does not end on
+// them.  For range filters the broad ones search longer (the log estimate
+// correlates +0.26 to +0.55 with a query's expansions), for label-based
+// filters (label, subset, Boolean, truth table) the narrow ones (-0.24 for
+// labels, -0.18 for Boolean filters, about 0 for subsets), so range filters
+// rank broadest first and the others narrowest first.  class_kernel, one
+// thread per query, first copies these classes out of the 128-byte
+// records, so that the sort reads 4 bytes per query (one compute unit
+// reading every record line itself takes 35 us at 10,000 queries).  The sort is one workgroup; thread t owns queries t, t + 512,
 // t + 1024, ... (coalesced reads), taken 16 at a time so that 16
 // independent loads are in flight per thread; within a class the order is
 // (thread, then position), not the query order, which no result depends on.
@@ -963,7 +966,8 @@ __global__ __launch_bounds__(256) void class_kernel(const FilterRecord *rec, int
     if (i >= nq) return;
     const float x = rec[i].sel_feature;  // log2(selectivity) / 16, in [-1.9, 0]
     const float c = floorf(16.f + x * (256.f / 30.f));
-    key[i] = c >= 0.f ? (int)c : 0;
+    const int broad = c >= 0.f ? (c <= 16.f ? (int)c : 16) : 0;  // 16: selectivity 1
+    key[i] = rec[i].type == F_RANGE ? broad : 16 - broad;
 }
 
 __device__ __forceinline__ int order_class(const int32_t *key, int64_t i)
@@ -1429,7 +1433,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     if (nq == 0) return JAG_OK;
     hipStream_t sm = (hipStream_t)stream;
     if (sel_ordered(S, nq)) {
-        // one launch, broadest filters first
+        // one launch, the searches expected to be long first
         keep_pool_reserved(ix.device);
         int32_t *perm = nullptr;
         HIPCHK(hipMallocAsync((void **)&perm, 2 * sizeof(int32_t) * (size_t)nq, sm));

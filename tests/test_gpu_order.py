@@ -1,6 +1,7 @@
 """Launch order of large batches: a fixed-beam or one-pass learned launch of at
-least 4096 queries runs its queries broadest filter first (a device counting
-sort over selectivity classes).  No answer may depend on that order: one
+least 4096 queries runs the searches expected to be long first (a device
+counting sort over selectivity classes: range filters broadest first, the
+label-based ones narrowest first).  No answer may depend on that order: one
 launch of 4,640 queries must return, query for query, what launches of fewer
 than 4096 queries (submission order) return."""
 import sys
