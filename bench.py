@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--delta", type=float, default=0.0)
     ap.add_argument("--ladder", default=None,
                     help="profile mode, learned: comma-separated ladder (as the bench line reports it)")
+    ap.add_argument("--ladder-top", type=int, default=None,
+                    help="widest beam of the learned ladder (default: 1.4x the fixed beam at recall 0.95)")
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson arrivals)")
     ap.add_argument("--rates", default="5000,20000,50000,100000,200000")
@@ -134,18 +136,33 @@ LADDER_FIXED = [10, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 56, 64, 80, 96, 128,
                 768, 1024]
 
 
-def learned_ladder(L95):
+def learned_ladder(L95, top=None):
     """Beams the predictor chooses from, sized to the workload: up to the
     smallest sweep beam >= 1.4x the fixed beam that reaches recall 0.95 (at
-    least 64, all of them if none does), at most 16 entries spaced evenly in
-    log scale.  On the range workload this gives a ladder topping at 64,
-    which measured better than one to 128."""
-    top = 1024 if L95 is None else next((L for L in LADDER_FIXED if L >= max(64, 1.4 * L95)), 1024)
+    least 64, all of them if none does; `top` overrides), at most 16 entries
+    spaced evenly in log scale.  On the range workload this gives a ladder
+    topping at 64, which measured better than one to 128."""
+    if top is None:
+        top = 1024 if L95 is None else next((L for L in LADDER_FIXED if L >= max(64, 1.4 * L95)), 1024)
     cand = [L for L in LADDER_FIXED if L <= top]
     if len(cand) > 16:
         want = np.exp(np.linspace(np.log(cand[0]), np.log(top), 16))
         cand = sorted({min(cand, key=lambda L: abs(np.log(L) - np.log(x))) for x in want})
     return np.array(cand, dtype=np.int32)
+
+def ladder_tops(L95, top=None):
+    """Widest ladder beams to try, narrowest first; the bench keeps the first
+    whose learned sweep reaches recall 0.95.  A narrow top keeps the widest
+    searches' lists short (more of them fit on the device at once), but a
+    top at the fixed beam itself can leave the learned search just below
+    0.95.  From max(64, that fixed beam) up to the default top."""
+    if top is not None:
+        return [top]
+    if L95 is None:
+        return [None]
+    hi = int(learned_ladder(L95)[-1])
+    return [L for L in LADDER_FIXED if max(64, L95) <= L <= hi] or [hi]
+
 
 # (attribute kind, quantile) lists: 0 scalar, 1 labels |a XOR b|, 2 labels with
 # the frequency-weighted distance the paper uses for skewed label vocabularies
@@ -493,20 +510,25 @@ def main():
     if not args.only_fixed:
         t3 = time.time()
         Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
-        lad = learned_ladder(next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None))
-        log(f"learned ladder {lad.tolist()}")
-        P, rho, fit_rep = pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4,
-                                   dump=args.dump_traces, ladder=lad)
-        log(f"predictor fitted on {fit_rep.n_train} traces in {time.time() - t3:.1f}s: loss "
-            f"{fit_rep.loss_first:.3f} -> {fit_rep.loss_last:.3f}, rho={rho:.2f}, "
-            f"unreachable={fit_rep.unreachable}")
-        for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0]:
-            r = point(ix16, rec16, jag.SearchParams(L=k, learned=1, delta=delta, rerank_mult=4))
-            r["delta"] = delta
-            learned.append(r)
-            log(f"learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} qps={r['qps']:.0f} "
-                f"mean Lhat={r['lhat']:.1f}")
-            if r["recall"] >= 0.995:
+        L95 = next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None)
+        for top in ladder_tops(L95, args.ladder_top):
+            lad = learned_ladder(L95, top)
+            log(f"learned ladder {lad.tolist()}")
+            P, rho, fit_rep = pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4,
+                                       dump=args.dump_traces, ladder=lad)
+            log(f"predictor fitted on {fit_rep.n_train} traces in {time.time() - t3:.1f}s: loss "
+                f"{fit_rep.loss_first:.3f} -> {fit_rep.loss_last:.3f}, rho={rho:.2f}, "
+                f"unreachable={fit_rep.unreachable}")
+            learned = []
+            for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0]:
+                r = point(ix16, rec16, jag.SearchParams(L=k, learned=1, delta=delta, rerank_mult=4))
+                r["delta"] = delta
+                learned.append(r)
+                log(f"learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} qps={r['qps']:.0f} "
+                    f"mean Lhat={r['lhat']:.1f}")
+                if r["recall"] >= 0.995:
+                    break
+            if any(r["recall"] >= 0.95 for r in learned):
                 break
 
     def at95(curve):

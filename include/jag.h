@@ -310,8 +310,9 @@ jag_status jag_encode_filters_sized(const jag_index *idx, const jag_filter *F, i
  * long first, by classes of the records' selectivity estimate (range
  * filters broadest first, label-based filters narrowest first), so that
  * the batch does not end on a few long searches; it takes nq * 8 bytes of
- * stream-ordered device scratch for the order.  No result depends on the
- * order.
+ * stream-ordered device scratch for the order (if that cannot be
+ * allocated, the batch runs in submission order).  No result depends on
+ * the order.
  * Errors: EINVAL (k < 1, k > 64, L < k, L > 1024, bad params),
  * EUNSUPPORTED (rerank without an FP32 copy, learned without predictor),
  * EDEVICE.

@@ -1432,25 +1432,30 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     if (st != JAG_OK) return st;
     if (nq == 0) return JAG_OK;
     hipStream_t sm = (hipStream_t)stream;
+    int32_t *order = nullptr;
     if (sel_ordered(S, nq)) {
-        // one launch, the searches expected to be long first
         keep_pool_reserved(ix.device);
-        int32_t *perm = nullptr;
-        HIPCHK(hipMallocAsync((void **)&perm, 2 * sizeof(int32_t) * (size_t)nq, sm));
-        int32_t *key = perm + nq;
+        if (hipMallocAsync((void **)&order, 2 * sizeof(int32_t) * (size_t)nq, sm) != hipSuccess) {
+            (void)hipGetLastError();  // no memory for the order: submission order below
+            order = nullptr;
+        }
+    }
+    if (order) {
+        // one launch, the searches expected to be long first
+        int32_t *key = order + nq;
         hipLaunchKernelGGL(class_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, sm, a.rec, nq, key);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, key, nq, perm);
+            hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, key, nq, order);
             e = hipGetLastError();
         }
         if (e == hipSuccess) {
             SearchArgs b = a;
-            b.perm = perm;
+            b.perm = order;
             hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, sm, b);
             e = hipGetLastError();
         }
-        hipError_t ef = hipFreeAsync(perm, sm);
+        hipError_t ef = hipFreeAsync(order, sm);
         HIPCHK(e);
         HIPCHK(ef);
         return JAG_OK;
