@@ -207,8 +207,9 @@ def parse_thresholds(text: str):
 
 def measured_traffic(workload: str, op_name: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, only if it was taken on this exact kernel source and operating
-    point; otherwise None."""
+    summaries (one entry, or a list of entries, one per operating point),
+    only if taken on this exact kernel source and operating point;
+    otherwise None."""
     import hashlib
     p = os.path.join(ROOT, "profiles", f"search_kernel_{workload}_counters.json")
     src = os.path.join(ROOT, "paper_2602_10258_amd", "csrc", "search.hip")
@@ -216,9 +217,10 @@ def measured_traffic(workload: str, op_name: str):
         return None
     d = json.load(open(p))
     sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
-    if d.get("search_hip_sha1") != sha or d.get("operating_point") != op_name:
-        return None
-    return d["traffic_bytes_per_launch"]
+    for e in d if isinstance(d, list) else [d]:
+        if e.get("search_hip_sha1") == sha and e.get("operating_point") == op_name:
+            return e["traffic_bytes_per_launch"]
+    return None
 
 
 def serve_main(args):
