@@ -943,10 +943,11 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
 // rank broadest first and the others narrowest first.  class_kernel, one
 // thread per query, first copies these classes out of the 128-byte
 // records, so that the sort reads 4 bytes per query (one compute unit
-// reading every record line itself takes 35 us at 10,000 queries).  The sort is one workgroup; thread t owns queries t, t + 512,
-// t + 1024, ... (coalesced reads), taken 16 at a time so that 16
-// independent loads are in flight per thread; within a class the order is
-// (thread, then position), not the query order, which no result depends on.
+// reading every record line itself takes 35 us at 10,000 queries).
+// The sort is one workgroup; thread t owns queries t, t + 512, t + 1024,
+// ... (coalesced reads), taken 16 at a time so that 16 independent loads
+// are in flight per thread; within a class the order is (thread, then
+// position), not the query order, which no result depends on.
 constexpr int kOrderThreads = 512;
 constexpr int kOrderBatch = 16;
 constexpr int kOrderBins = JAG_LADDER_MAX + 1;
