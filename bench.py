@@ -285,20 +285,24 @@ def serve_main(args):
         if recall_of(ids.cpu().numpy()) >= 0.95:
             L95 = L
             break
-    lad = learned_ladder(L95)
-    log(f"fixed beam at recall 0.95: {L95}; learned ladder {lad.tolist()}")
-    _, rho, rep = pred.fit(ix, Qt, Ft, pt, k=k, rerank_mult=4, ladder=lad)
-    log(f"predictor: loss {rep.loss_first:.2f} -> {rep.loss_last:.2f}, rho {rho:.2f}")
-    # the smallest offset reaching recall 0.95 on the batch path
+    # the narrowest ladder top whose learned search reaches 0.95 on the
+    # batch path (as in the main sweep); the smallest offset reaching it
     delta = None
-    for dl in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]:
-        sp = jag.SearchParams(L=k, learned=1, delta=dl, rerank_mult=4)
-        jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, dd, cnt)
-        torch.cuda.synchronize()
-        r = recall_of(ids.cpu().numpy())
-        log(f"delta {dl:+.1f}: batch recall {r:.4f}")
-        if r >= 0.95:
-            delta = dl
+    for top in ladder_tops(L95, args.ladder_top):
+        lad = learned_ladder(L95, top)
+        log(f"fixed beam at recall 0.95: {L95}; learned ladder {lad.tolist()}")
+        _, rho, rep = pred.fit(ix, Qt, Ft, pt, k=k, rerank_mult=4, ladder=lad)
+        log(f"predictor: loss {rep.loss_first:.2f} -> {rep.loss_last:.2f}, rho {rho:.2f}")
+        for dl in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]:
+            sp = jag.SearchParams(L=k, learned=1, delta=dl, rerank_mult=4)
+            jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, dd, cnt)
+            torch.cuda.synchronize()
+            r = recall_of(ids.cpu().numpy())
+            log(f"delta {dl:+.1f}: batch recall {r:.4f}")
+            if r >= 0.95:
+                delta = dl
+                break
+        if delta is not None:
             break
     if delta is None:
         delta = 6.0
