@@ -300,6 +300,7 @@ typedef struct {
     double margin;
     double y;
     int32_t lhat;
+    double feat[16]; /* predictor features at the prediction point (NaN if none) */
 } or_trace;
 
 /* per-thread membership stamps for L and V (sized n) */
@@ -400,6 +401,7 @@ static int32_t greedy_search(const or_graph *G, const float *x, first_fn first, 
     if (tr) {
         tr->y = NAN;
         tr->lhat = -1;
+        for (int i = 0; i < 16; i++) tr->feat[i] = NAN;
     }
     S->stamp++;
     int32_t st = S->stamp;
@@ -465,6 +467,7 @@ static int32_t greedy_search(const or_graph *G, const float *x, first_fn first, 
             if (tr) {
                 tr->y = y;
                 tr->lhat = lhat;
+                memcpy(tr->feat, feat, sizeof(feat));
             }
             float capf = ceilf(M->rho * (float)lhat);
             hopcap = capf >= 2147483647.0f ? INT32_MAX : (int32_t)capf;
@@ -521,6 +524,7 @@ typedef struct {
     int32_t *count;
     int32_t *hops, *dc, *lhat;
     double *margin, *y;
+    double *feat; /* [nq][16] or NULL */
     int64_t q0, q1;
 } search_job;
 
@@ -571,6 +575,7 @@ static void query_one(search_job *J, int64_t q, or_scratch *S)
     if (J->margin) J->margin[q] = margin;
     if (J->y) J->y[q] = tr.y;
     if (J->lhat) J->lhat[q] = tr.lhat;
+    if (J->feat) memcpy(J->feat + q * 16, tr.feat, sizeof(tr.feat));
     free(L);
 }
 
@@ -596,7 +601,9 @@ static void run_jobs(void *(*fn)(void *), void *jobs, size_t jsz, int32_t nthrea
 /*
  * Batched Query.  Queries are independent, so they are spread over
  * `nthreads` threads; each query runs the sequential algorithm above.
- * learned_params == NULL disables the predictor.
+ * learned_params == NULL disables the predictor; with it, feat (optional,
+ * [nq][16]) receives each query's features at the prediction point (NaN
+ * for a query that ended before its fourth expansion).
  */
 int or_search(int64_t n, int32_t d, const float *base, const int32_t *adj, int32_t R,
               int32_t entry, const int32_t *scalar, const int64_t *loff, const int32_t *lab,
@@ -604,7 +611,8 @@ int or_search(int64_t n, int32_t d, const float *base, const int32_t *adj, int32
               int32_t k, const float *rerank, int32_t rerank_mult, const float *learned_params,
               float delta, float rho, int32_t nladder, const int32_t *ladder,
               const float *sel_feature, int32_t nthreads, int32_t *ids, double *d2, int32_t *count,
-              int32_t *hops, int32_t *dc, double *margin, double *y, int32_t *lhat)
+              int32_t *hops, int32_t *dc, double *margin, double *y, int32_t *lhat,
+              double *feat)
 {
     if (nthreads < 1) nthreads = 1;
     if (nq < nthreads) nthreads = (int32_t)(nq > 0 ? nq : 1);
@@ -631,6 +639,7 @@ int or_search(int64_t n, int32_t d, const float *base, const int32_t *adj, int32
         J->margin = margin;
         J->y = y;
         J->lhat = lhat;
+        J->feat = feat;
         J->q0 = nq * t / nthreads;
         J->q1 = nq * (t + 1) / nthreads;
     }
@@ -988,11 +997,16 @@ static void point_thresholds(build_state *B, const double *quant, uint64_t seed)
  * points follow in a seeded random order.  Writes adj[n][R] (-1 padded) and
  * returns the entry vertex; thr_out (the per-point thresholds) and
  * order_out (the insertion order) are optional.
+ * Optional inputs: order_in, an insertion order (a permutation of 0..n-1
+ * starting with the entry vertex) used instead of the seeded one, and
+ * thr_in[n][nT], per-point threshold values used instead of the sampled
+ * quantiles.  Returns -1 when order_in is not such a permutation.
  */
 int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, const int64_t *loff,
                  const int32_t *lab, int32_t R, int32_t lb, double alpha, int32_t nT,
                  const int32_t *kinds, const double *quant, uint64_t seed, int32_t *adj,
-                 double *thr_out, int32_t *order_out)
+                 double *thr_out, int32_t *order_out, const int32_t *order_in,
+                 const double *thr_in)
 {
     build_state B;
     B.n = n;
@@ -1031,18 +1045,38 @@ int32_t or_build(int64_t n, int32_t d, const float *X, const int32_t *scalar, co
     }
     free(cen);
     B.entry = s;
-    point_thresholds(&B, quant, seed);
+    if (thr_in) memcpy(B.thr, thr_in, sizeof(double) * (size_t)n * (size_t)nT);
+    else point_thresholds(&B, quant, seed);
 
     int32_t *order = malloc(sizeof(int32_t) * (size_t)n);
-    int64_t m = 0;
-    order[m++] = s;
-    for (int64_t i = 0; i < n; i++)
-        if (i != s) order[m++] = (int32_t)i;
-    for (int64_t i = n - 1; i > 1; i--) { /* Fisher-Yates over positions 1..n-1 */
-        int64_t j = 1 + (int64_t)(splitmix64(seed + 0x5bd1e995ull * (uint64_t)i) % (uint64_t)i);
-        int32_t t = order[i];
-        order[i] = order[j];
-        order[j] = t;
+    if (order_in) {
+        char *seen = calloc((size_t)n, 1);
+        int ok = order_in[0] == s;
+        for (int64_t i = 0; i < n && ok; i++) {
+            int32_t v = order_in[i];
+            ok = v >= 0 && v < n && !seen[v];
+            if (ok) seen[v] = 1;
+        }
+        free(seen);
+        if (!ok) {
+            free(order);
+            free(B.thr);
+            free(B.deg);
+            free(lw);
+            return -1;
+        }
+        memcpy(order, order_in, sizeof(int32_t) * (size_t)n);
+    } else {
+        int64_t m = 0;
+        order[m++] = s;
+        for (int64_t i = 0; i < n; i++)
+            if (i != s) order[m++] = (int32_t)i;
+        for (int64_t i = n - 1; i > 1; i--) { /* Fisher-Yates over positions 1..n-1 */
+            int64_t j = 1 + (int64_t)(splitmix64(seed + 0x5bd1e995ull * (uint64_t)i) % (uint64_t)i);
+            int32_t t = order[i];
+            order[i] = order[j];
+            order[j] = t;
+        }
     }
 
     or_scratch S;
@@ -1173,6 +1207,16 @@ void or_fp8_decode_rows(int64_t n, int32_t d, const uint8_t *codes, const float 
 /* ------------------------------------------------------------------ */
 /* Beam predictor network in FP64 (not in the paper)                  */
 /* ------------------------------------------------------------------ */
+
+/*
+ * The network output y for each of B feature rows X[B][16], with the FP32
+ * parameters the learned search uses (the forward pass above, exported so
+ * that it can be checked on its own).
+ */
+void or_mlp_forward(const float *P, int64_t B, const double *X, double *Y)
+{
+    for (int64_t b = 0; b < B; b++) Y[b] = mlp_forward(P, X + b * 16);
+}
 
 /*
  * Mean squared error of a 16-64-64-1 ReLU network over a batch, and its

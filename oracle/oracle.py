@@ -5,9 +5,10 @@ baseline leg of the benchmark use this module.  The product library never
 imports it.  See ``jag_oracle.c`` for what each routine computes and which
 part of the paper it follows.
 
-Parity status: every routine here is pinned by ``tests/test_oracle_*.py``
-except the graph builder (no reference graph exists; it is checked through
-structural invariants and recall only -- parity unpinned).
+Parity status: every routine here is pinned by ``tests/test_oracle_*.py``;
+the graph builder by graphs worked out by hand on two five-point worlds
+(``tests/golden/build_line_worlds.txt``) besides structural invariants and
+recall.
 """
 from __future__ import annotations
 
@@ -50,7 +51,7 @@ def lib():
         P = C.c_void_p
         i64, i32, f64, f32, u64 = C.c_int64, C.c_int32, C.c_double, C.c_float, C.c_uint64
         L.or_search.argtypes = [i64, i32, P, P, i32, i32, P, P, P, i64, P, P, P, i32, i32, P, i32,
-                                P, f32, f32, i32, P, P, i32, P, P, P, P, P, P, P, P]
+                                P, f32, f32, i32, P, P, i32, P, P, P, P, P, P, P, P, P]
         L.or_search.restype = C.c_int
         L.or_bruteforce.argtypes = [i64, i32, P, P, P, P, i64, P, P, P, i32, i32, P, P, P]
         L.or_bruteforce.restype = C.c_int
@@ -58,7 +59,7 @@ def lib():
         L.or_dist_f_pairs.restype = None
         L.or_dist_a_pairs.argtypes = [i64, P, P, P, i32, i64, P, P, f64, P]
         L.or_dist_a_pairs.restype = None
-        L.or_build.argtypes = [i64, i32, P, P, P, P, i32, i32, f64, i32, P, P, u64, P, P, P]
+        L.or_build.argtypes = [i64, i32, P, P, P, P, i32, i32, f64, i32, P, P, u64, P, P, P, P, P]
         L.or_build.restype = i32
         L.or_prune.argtypes = [i64, i32, P, P, P, P, i32, f64, i32, P, P, i32, P, i32, P]
         L.or_prune.restype = i32
@@ -72,6 +73,8 @@ def lib():
         L.or_fp8_encode_rows.restype = None
         L.or_fp8_decode_rows.argtypes = [i64, i32, P, P, P]
         L.or_fp8_decode_rows.restype = None
+        L.or_mlp_forward.argtypes = [P, i64, P, P]
+        L.or_mlp_forward.restype = None
         L.or_mlp_loss_grad.argtypes = [P, i64, P, P, P, P]
         L.or_mlp_loss_grad.restype = f64
         _lib = L
@@ -135,19 +138,29 @@ def _out_i32(a: Optional[np.ndarray], n: int):
 
 
 def build(X, attrs: Attrs, R: int, L_build: int, alpha: float, kinds, quantiles,
-          seed: int = 0, order_out: Optional[np.ndarray] = None):
+          seed: int = 0, order_out: Optional[np.ndarray] = None, order=None, thresholds=None):
     """Sequential Threshold-JAG build (Algorithms 3-4).  Returns (adj, entry, thr);
-    the insertion order goes to order_out (int32 [n]) when given."""
+    the insertion order goes to order_out (int32 [n]) when given.  ``order``
+    (a permutation starting with the entry vertex) and ``thresholds``
+    (float64 [n][|T|]) replace the seeded order and the sampled thresholds."""
     X = _c(X, np.float32)
     n, d = X.shape
     s, lo, lb = attrs.arrays()
     kinds = _c(kinds, np.int32)
     quant = _c(quantiles, np.float64)
+    order = _c(order, np.int32)
+    thr_in = _c(thresholds, np.float64)
+    if order is not None and order.shape != (n,):
+        raise ValueError("order must hold n entries")
+    if thr_in is not None and thr_in.shape != (n, len(kinds)):
+        raise ValueError("thresholds must be [n][len(kinds)]")
     adj = np.empty((n, R), dtype=np.int32)
     thr = np.empty((n, len(kinds)), dtype=np.float64)
     entry = lib().or_build(n, d, _p(X), _p(s), _p(lo), _p(lb), R, L_build, float(alpha),
                            len(kinds), _p(kinds), _p(quant), seed, _p(adj), _p(thr),
-                           _p(_out_i32(order_out, n)))
+                           _p(_out_i32(order_out, n)), _p(order), _p(thr_in))
+    if entry < 0:
+        raise ValueError("order is not a permutation starting with the entry vertex")
     return adj, int(entry), thr
 
 
@@ -175,6 +188,7 @@ class SearchResult:
     margin: np.ndarray
     y: np.ndarray
     lhat: np.ndarray
+    feat: np.ndarray  # [nq][16] predictor features (NaN without a predictor)
 
 
 def search(base, adj, entry, attrs: Attrs, Q, F, pool, L: int, k: int, rerank=None,
@@ -209,11 +223,12 @@ def search(base, adj, entry, attrs: Attrs, Q, F, pool, L: int, k: int, rerank=No
     margin = np.empty(nq, dtype=np.float64)
     y = np.empty(nq, dtype=np.float64)
     lhat = np.empty(nq, dtype=np.int32)
+    feat = np.full((nq, 16), np.nan, dtype=np.float64)
     lib().or_search(n, d, _p(base), _p(adj), R, entry, _p(s), _p(lo), _p(lb), nq, _p(Q), _p(F),
                     _p(pool), L, k, _p(rerank), rerank_mult, _p(learned), float(delta),
                     float(rho), len(ladder), _p(ladder), _p(self_), nthreads, _p(ids), _p(d2),
-                    _p(count), _p(hops), _p(dc), _p(margin), _p(y), _p(lhat))
-    return SearchResult(ids, d2, count, hops, dc, margin, y, lhat)
+                    _p(count), _p(hops), _p(dc), _p(margin), _p(y), _p(lhat), _p(feat))
+    return SearchResult(ids, d2, count, hops, dc, margin, y, lhat, feat)
 
 
 def bruteforce(X, attrs: Attrs, Q, F, pool, k: int, nthreads: int = 1):
@@ -299,6 +314,15 @@ def fp8_decode_rows(codes, scales):
     X = np.empty((n, d), dtype=np.float32)
     lib().or_fp8_decode_rows(n, d, _p(codes), _p(scales), _p(X))
     return X
+
+
+def mlp_forward(params, X) -> np.ndarray:
+    """Network output of the learned search's forward pass (FP32 parameters, FP64 sums)."""
+    P = _c(params, np.float32)
+    X = _c(X, np.float64)
+    Y = np.empty(X.shape[0], dtype=np.float64)
+    lib().or_mlp_forward(_p(P), X.shape[0], _p(X), _p(Y))
+    return Y
 
 
 def mlp_loss_grad(params, X, T):

@@ -16,7 +16,7 @@ import pytest
 from paper_2602_10258_amd import jag
 from workloads import make_config
 
-from .test_build_parity import CASES, oracle_graph, small_world
+from .test_build_parity import CASES, WEIGHTED_CASES, oracle_graph, small_world, weighted_oracle_graph
 
 pytestmark = pytest.mark.gpu
 
@@ -36,6 +36,18 @@ def test_device_rounds_of_one_give_the_oracle_graph(case):
     oadj, oentry, tv, order = oracle_graph(X, scal, loff, lab, R, lb, thr, seed=3)
     _say("device build, rounds of one:", case, n, d, R)
     adj, entry = jag.jag_build_graph(X, scalar=scal, label_off=loff, labels=lab, vocab=12, R=R, L_build=lb,
+                                     thresholds=thr, max_batch=1, order=order, thr_values=tv, device=True)
+    assert entry == oentry
+    assert np.array_equal(adj, oadj), f"{np.sum(np.any(adj != oadj, axis=1))} rows differ"
+
+
+@pytest.mark.parametrize("case", sorted(WEIGHTED_CASES))
+def test_device_weighted_labels_rounds_of_one_give_the_oracle_graph(case):
+    """App. D.3's frequency-weighted label distance, with thresholds halfway
+    between consecutive distinct distances (see test_build_parity)."""
+    X, scal, loff, lab, R, lb, thr, tv, order, oadj, oentry = weighted_oracle_graph(case)
+    _say("device build, rounds of one, weighted labels:", case, X.shape, R)
+    adj, entry = jag.jag_build_graph(X, scalar=scal, label_off=loff, labels=lab, vocab=24, R=R, L_build=lb,
                                      thresholds=thr, max_batch=1, order=order, thr_values=tv, device=True)
     assert entry == oentry
     assert np.array_equal(adj, oadj), f"{np.sum(np.any(adj != oadj, axis=1))} rows differ"
