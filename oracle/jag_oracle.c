@@ -233,6 +233,46 @@ static double sqdist(const float *x, const float *y, int32_t d)
     return s;
 }
 
+/*
+ * Optional FP32 evaluation order ("contract mode").  A row of d values is
+ * split over G lanes: lane s takes the EPC consecutive elements of chunks
+ * j*G + s, j = 0..CH-1, and folds (x - y)^2 of each into its FP32 partial
+ * sum with one fused multiply-add, in chunk then element order (elements
+ * at or beyond d add nothing); the G partial sums are then added pairwise,
+ * neighbours first: ((p0 + p1) + (p2 + p3)) + ...  An implementation that
+ * evaluates distances in this documented order obtains the same FP32 value
+ * bit for bit, so its search can be compared with this one id for id with
+ * no tolerance.  The FP64 sum above remains the reference for accuracy.
+ */
+typedef struct {
+    int32_t G, EPC, CH;
+} or_contract;
+
+static double sqdist_contract(const float *x, const float *y, int32_t d, const or_contract *c)
+{
+    float part[64];
+    for (int32_t s = 0; s < c->G; s++) {
+        float acc = 0.0f;
+        for (int32_t j = 0; j < c->CH; j++)
+            for (int32_t e = 0; e < c->EPC; e++) {
+                int32_t i = (j * c->G + s) * c->EPC + e;
+                if (i < d) {
+                    float t = x[i] - y[i];
+                    acc = fmaf(t, t, acc);
+                }
+            }
+        part[s] = acc;
+    }
+    for (int32_t m = 1; m < c->G; m <<= 1)
+        for (int32_t s = 0; s < c->G; s += 2 * m) part[s] = part[s] + part[s + m];
+    return (double)part[0];
+}
+
+static double search_dist(const float *x, const float *y, int32_t d, const or_contract *c)
+{
+    return c ? sqdist_contract(x, y, d, c) : sqdist(x, y, d);
+}
+
 /* ------------------------------------------------------------------ */
 /* Lexicographic keys (Section 3.2), ties broken by id                */
 /* ------------------------------------------------------------------ */
@@ -281,6 +321,7 @@ typedef struct {
     int32_t entry;
     const float *base; /* vectors the search ranks by, [n][d] */
     int32_t d;
+    const or_contract *contract; /* NULL: FP64 distances */
 } or_graph;
 
 typedef struct { /* learned beam predictor (not in the paper) */
@@ -409,7 +450,7 @@ static int32_t greedy_search(const or_graph *G, const float *x, first_fn first, 
     /* L <- {s}, V <- {} */
     L[0].id = G->entry;
     L[0].f = first(ctx, G->entry);
-    L[0].d2 = sqdist(x, G->base + (size_t)G->entry * G->d, G->d);
+    L[0].d2 = search_dist(x, G->base + (size_t)G->entry * G->d, G->d, G->contract);
     dc++;
     S->inL[G->entry] = st;
     nL = 1;
@@ -443,7 +484,7 @@ static int32_t greedy_search(const or_graph *G, const float *x, first_fn first, 
             or_key c;
             c.id = u;
             c.f = first(ctx, u);
-            c.d2 = sqdist(x, G->base + (size_t)u * G->d, G->d);
+            c.d2 = search_dist(x, G->base + (size_t)u * G->d, G->d, G->contract);
             dc++;
             L[nL++] = c;
             S->inL[u] = st;
@@ -515,6 +556,7 @@ typedef struct {
     const int32_t *pool;
     const float *rerank; /* FP32 vectors for the final rescoring, or NULL */
     int32_t rerank_mult;
+    const or_contract *rerank_contract; /* NULL: FP64 distances */
     int32_t ls, k;
     const float *sel_feature; /* [nq] */
     or_learned M;
@@ -553,7 +595,7 @@ static void query_one(search_job *J, int64_t q, or_scratch *S)
             nres = rk;
         }
         for (int32_t j = 0; j < nres; j++)
-            L[j].d2 = sqdist(x, J->rerank + (size_t)L[j].id * J->G.d, J->G.d);
+            L[j].d2 = search_dist(x, J->rerank + (size_t)L[j].id * J->G.d, J->G.d, J->rerank_contract);
         qsort(L, (size_t)nres, sizeof(or_key), key_cmp);
     }
     /* top-k of V by D_F equals the top-k of the final L; only valid ids are returned */
@@ -603,7 +645,9 @@ static void run_jobs(void *(*fn)(void *), void *jobs, size_t jsz, int32_t nthrea
  * `nthreads` threads; each query runs the sequential algorithm above.
  * learned_params == NULL disables the predictor; with it, feat (optional,
  * [nq][16]) receives each query's features at the prediction point (NaN
- * for a query that ended before its fourth expansion).
+ * for a query that ended before its fourth expansion).  contract (optional)
+ * = {G, EPC, CH} of the ranking vectors then of the rescoring vectors:
+ * distances in that FP32 order instead of FP64 (see sqdist_contract).
  */
 int or_search(int64_t n, int32_t d, const float *base, const int32_t *adj, int32_t R,
               int32_t entry, const int32_t *scalar, const int64_t *loff, const int32_t *lab,
@@ -612,14 +656,20 @@ int or_search(int64_t n, int32_t d, const float *base, const int32_t *adj, int32
               float delta, float rho, int32_t nladder, const int32_t *ladder,
               const float *sel_feature, int32_t nthreads, int32_t *ids, double *d2, int32_t *count,
               int32_t *hops, int32_t *dc, double *margin, double *y, int32_t *lhat,
-              double *feat)
+              double *feat, const int32_t *contract)
 {
+    or_contract cs, cr;
+    if (contract) {
+        cs = (or_contract){contract[0], contract[1], contract[2]};
+        cr = (or_contract){contract[3], contract[4], contract[5]};
+    }
     if (nthreads < 1) nthreads = 1;
     if (nq < nthreads) nthreads = (int32_t)(nq > 0 ? nq : 1);
     search_job *jobs = calloc((size_t)nthreads, sizeof(search_job));
     for (int32_t t = 0; t < nthreads; t++) {
         search_job *J = &jobs[t];
-        J->G = (or_graph){adj, R, n, entry, base, d};
+        J->G = (or_graph){adj, R, n, entry, base, d, contract ? &cs : NULL};
+        J->rerank_contract = contract ? &cr : NULL;
         J->A = (or_attrs){n, scalar, loff, lab, NULL, 0.0};
         J->Q = Q;
         J->F = (const or_filter *)F;
@@ -718,6 +768,87 @@ int or_bruteforce(int64_t n, int32_t d, const float *X, const int32_t *scalar,
     run_jobs(bf_worker, jobs, sizeof(bf_job), nthreads);
     free(jobs);
     return 0;
+}
+
+/*
+ * Selectivity estimate of each filter (the paper has none; the learned
+ * search's feature 4): the fraction of items the filter passes, exact for
+ * label and range filters (a count), and for subset, DNF and truth-table
+ * filters the probability that an item passes when each label is held
+ * independently with its observed frequency: every assignment of the
+ * filter's distinct labels is enumerated, weighted by the product of the
+ * frequencies, and counted when the filter holds on it.
+ */
+void or_selectivity(int64_t n, const int32_t *scalar, const int64_t *loff, const int32_t *lab,
+                    int64_t nq, const int32_t *F, const int32_t *pool, double *out)
+{
+    or_attrs A = {n, scalar, loff, lab, NULL, 0.0};
+    int32_t vocab = 0;
+    if (loff)
+        for (int64_t x = 0; x < loff[n]; x++)
+            if (lab[x] + 1 > vocab) vocab = lab[x] + 1;
+    double *freq = calloc((size_t)(vocab > 0 ? vocab : 1), sizeof(double));
+    if (loff)
+        for (int64_t x = 0; x < loff[n]; x++) freq[lab[x]] += 1.0 / (double)n;
+    for (int64_t q = 0; q < nq; q++) {
+        const or_filter *f = (const or_filter *)F + q;
+        if (f->type == OR_F_RANGE || f->type == OR_F_LABEL) {
+            int64_t c = 0;
+            for (int64_t i = 0; i < n; i++) c += dist_f(&A, i, f, pool) == 0.0;
+            out[q] = (double)c / (double)n;
+            continue;
+        }
+        /* the filter's distinct labels v_0..v_{m-1} */
+        int32_t vars[32], m = 0;
+        const int32_t *p = pool + f->off;
+        int32_t nlab = 0;
+        const int32_t *labs = NULL;
+        if (f->type == OR_F_SUBSET) {
+            labs = p;
+            nlab = f->len;
+        } else if (f->type == OR_F_TABLE) {
+            labs = p + 1;
+            nlab = p[0];
+        }
+        for (int32_t j = 0; j < nlab; j++) {
+            int dup = 0;
+            for (int32_t x = 0; x < m; x++) dup |= vars[x] == labs[j];
+            if (!dup) vars[m++] = labs[j];
+        }
+        if (f->type == OR_F_BOOLEAN) {
+            int32_t ncl = p[0], pos = 1;
+            for (int32_t c = 0; c < ncl; c++) {
+                int32_t nl = p[pos++];
+                for (int32_t j = 0; j < nl; j++) {
+                    int32_t l = p[pos + j] >= 0 ? p[pos + j] : ~p[pos + j];
+                    int dup = 0;
+                    for (int32_t x = 0; x < m; x++) dup |= vars[x] == l;
+                    if (!dup) vars[m++] = l;
+                }
+                pos += nl;
+            }
+        }
+        /* enumerate assignments: a one-item world holding exactly the labels set in x */
+        double total = 0.0;
+        int32_t one_lab[32];
+        int64_t one_off[2] = {0, 0};
+        or_attrs one = {1, NULL, one_off, one_lab, NULL, 0.0};
+        for (uint32_t x = 0; x < (1u << m); x++) {
+            double pr = 1.0;
+            int32_t c = 0;
+            for (int32_t v = 0; v < m; v++) {
+                if ((x >> v) & 1u) {
+                    pr *= freq[vars[v]];
+                    one_lab[c++] = vars[v];
+                } else
+                    pr *= 1.0 - freq[vars[v]];
+            }
+            one_off[1] = c;
+            if (dist_f(&one, 0, f, pool) == 0.0) total += pr;
+        }
+        out[q] = total;
+    }
+    free(freq);
 }
 
 /* dist_F for a list of (item, filter) pairs; exported for the distance tests */

@@ -51,7 +51,7 @@ def lib():
         P = C.c_void_p
         i64, i32, f64, f32, u64 = C.c_int64, C.c_int32, C.c_double, C.c_float, C.c_uint64
         L.or_search.argtypes = [i64, i32, P, P, i32, i32, P, P, P, i64, P, P, P, i32, i32, P, i32,
-                                P, f32, f32, i32, P, P, i32, P, P, P, P, P, P, P, P, P]
+                                P, f32, f32, i32, P, P, i32, P, P, P, P, P, P, P, P, P, P]
         L.or_search.restype = C.c_int
         L.or_bruteforce.argtypes = [i64, i32, P, P, P, P, i64, P, P, P, i32, i32, P, P, P]
         L.or_bruteforce.restype = C.c_int
@@ -73,6 +73,8 @@ def lib():
         L.or_fp8_encode_rows.restype = None
         L.or_fp8_decode_rows.argtypes = [i64, i32, P, P, P]
         L.or_fp8_decode_rows.restype = None
+        L.or_selectivity.argtypes = [i64, P, P, P, i64, P, P, P]
+        L.or_selectivity.restype = None
         L.or_mlp_forward.argtypes = [P, i64, P, P]
         L.or_mlp_forward.restype = None
         L.or_mlp_loss_grad.argtypes = [P, i64, P, P, P, P]
@@ -116,6 +118,24 @@ def dist_f(attrs: Attrs, items, F, fidx, pool) -> np.ndarray:
     lib().or_dist_f_pairs(attrs.n, _p(s), _p(lo), _p(lb), len(items), _p(items), _p(F),
                           _p(fidx), _p(pool), _p(out))
     return out
+
+
+def selectivity(attrs: Attrs, F, pool) -> np.ndarray:
+    """Selectivity estimate per filter: exact fraction for label and range
+    filters; for subset, DNF and table filters the probability of passing
+    when labels are held independently with their observed frequencies."""
+    s, lo, lb = attrs.arrays()
+    F = _c(F, np.int32)
+    pool = _c(pool, np.int32)
+    out = np.empty(F.shape[0], dtype=np.float64)
+    lib().or_selectivity(attrs.n, _p(s), _p(lo), _p(lb), F.shape[0], _p(F), _p(pool), _p(out))
+    return out
+
+
+def sel_feature(sel) -> np.ndarray:
+    """The predictor's selectivity feature log2(max(s, 1e-9)) / 16, as float32."""
+    sel = np.asarray(sel, dtype=np.float64)
+    return (np.log2(np.maximum(sel, 1e-9)) / 16.0).astype(np.float32)
 
 
 def dist_a(attrs: Attrs, kind: int, i1, i2, t: float = 0.0) -> np.ndarray:
@@ -193,14 +213,16 @@ class SearchResult:
 
 def search(base, adj, entry, attrs: Attrs, Q, F, pool, L: int, k: int, rerank=None,
            rerank_mult: int = 4, learned=None, delta: float = 0.0, rho: float = 1e9,
-           ladder=LADDER, sel_feature=None, nthreads: int = 1) -> SearchResult:
+           ladder=LADDER, sel_feature=None, nthreads: int = 1, contract=None) -> SearchResult:
     """Query (Algorithm 2 over Algorithm 1) for a batch of filtered queries.
 
     ``base`` holds the vectors the search ranks by (FP32, or the exact
     decoding of a BF16/FP8 store); ``rerank`` optionally holds FP32 vectors
     used to rescore the best ``rerank_mult * k`` entries of the final list.
     ``learned`` is a float32[5313] parameter vector enabling the beam
-    predictor.
+    predictor.  ``contract`` = (G, EPC, CH) of the ranking vectors followed
+    by those of the rescoring vectors selects FP32 distances in that lane
+    order instead of FP64 (see ``sqdist_contract`` in the C source).
     """
     base = _c(base, np.float32)
     n, d = base.shape
@@ -224,10 +246,13 @@ def search(base, adj, entry, attrs: Attrs, Q, F, pool, L: int, k: int, rerank=No
     y = np.empty(nq, dtype=np.float64)
     lhat = np.empty(nq, dtype=np.int32)
     feat = np.full((nq, 16), np.nan, dtype=np.float64)
+    con = None if contract is None else np.ascontiguousarray(contract, dtype=np.int32)
+    if con is not None and con.shape != (6,):
+        raise ValueError("contract holds six integers")
     lib().or_search(n, d, _p(base), _p(adj), R, entry, _p(s), _p(lo), _p(lb), nq, _p(Q), _p(F),
                     _p(pool), L, k, _p(rerank), rerank_mult, _p(learned), float(delta),
                     float(rho), len(ladder), _p(ladder), _p(self_), nthreads, _p(ids), _p(d2),
-                    _p(count), _p(hops), _p(dc), _p(margin), _p(y), _p(lhat), _p(feat))
+                    _p(count), _p(hops), _p(dc), _p(margin), _p(y), _p(lhat), _p(feat), _p(con))
     return SearchResult(ids, d2, count, hops, dc, margin, y, lhat, feat)
 
 

@@ -82,6 +82,18 @@ void copy_attrs(Index &ix, const jag_attrs *A)
         ix.scalar.assign(A->scalar, A->scalar + n);
         ix.scalar_sorted = ix.scalar;
         std::sort(ix.scalar_sorted.begin(), ix.scalar_sorted.end());
+        ix.scal_min = ix.scalar_sorted.front();
+        ix.scal_max = ix.scalar_sorted.back();
+        const int64_t span = ix.scal_max - ix.scal_min;
+        ix.scal_shift = 0;
+        while ((span >> ix.scal_shift) >= (int64_t(1) << 16)) ix.scal_shift++;
+        const int64_t nb = (span >> ix.scal_shift) + 1;
+        ix.scal_cum.assign((size_t)nb + 1, n);
+        int64_t b = 0;
+        for (int64_t i = 0; i < n; i++) {
+            const int64_t bi = ((int64_t)ix.scalar_sorted[i] - ix.scal_min) >> ix.scal_shift;
+            while (b <= bi) ix.scal_cum[(size_t)b++] = i;
+        }
     }
     if (A && A->label_off) {
         ix.has_labels = true;
@@ -129,6 +141,18 @@ jag_status finish(std::unique_ptr<jag_index> &h, const jag_build_params *P, jag_
 }
 
 // ---- selectivity estimate (used for the predictor's features) ----
+}  // namespace
+
+int64_t scalar_rank_below(const Index &ix, int64_t v)
+{
+    if (v <= ix.scal_min) return 0;
+    if (v > ix.scal_max) return ix.n;
+    const size_t b = (size_t)((v - ix.scal_min) >> ix.scal_shift);
+    const int32_t *base = ix.scalar_sorted.data();
+    return std::lower_bound(base + ix.scal_cum[b], base + ix.scal_cum[b + 1], v) - base;
+}
+
+namespace {
 double label_freq(const Index &ix, int32_t l)
 {
     return (double)ix.label_count[l] / (double)ix.n;
@@ -184,9 +208,9 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
             }
             r.a = f.lo;
             r.b = f.hi;
-            auto lo = std::lower_bound(ix.scalar_sorted.begin(), ix.scalar_sorted.end(), f.lo);
-            auto hi = std::upper_bound(ix.scalar_sorted.begin(), ix.scalar_sorted.end(), f.hi);
-            sel = f.hi < f.lo ? 0.0 : (double)(hi - lo) / (double)ix.n;
+            sel = f.hi < f.lo ? 0.0
+                              : (double)(scalar_rank_below(ix, (int64_t)f.hi + 1) - scalar_rank_below(ix, f.lo)) /
+                                    (double)ix.n;
         } else if (f.type == F_SUBSET) {
             if (!need_labels() || !check_span()) return JAG_EINVAL;
             if (f.len > kMaxFilterLits) {
@@ -333,15 +357,22 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
                         D[x | b] = (uint8_t)std::min(d1, std::min(d0 + 1, 255));
                     }
             }
-            double pf[kMaxTableVars];
-            for (int v = 0; v < nv; v++) pf[v] = label_freq(ix, r.lits[v]);
+            // probability of each assignment under independent labels, built
+            // by doubling (each product is formed in variable order, as a
+            // per-assignment loop would), summed over the true assignments
+            thread_local std::vector<double> pa;
+            pa.assign((size_t)N, 1.0);
+            for (int v = 0; v < nv; v++) {
+                const double pf = label_freq(ix, r.lits[v]);
+                const int b = 1 << v;
+                for (int x = 0; x < b; x++) {
+                    pa[(size_t)(x | b)] = pa[(size_t)x] * pf;
+                    pa[(size_t)x] = pa[(size_t)x] * (1.0 - pf);
+                }
+            }
             sel = 0.0;
             for (int x = 0; x < N; x++)
-                if ((w[x >> 5] >> (x & 31)) & 1u) {
-                    double pr = 1.0;
-                    for (int v = 0; v < nv; v++) pr *= ((x >> v) & 1) ? pf[v] : 1.0 - pf[v];
-                    sel += pr;
-                }
+                if ((w[x >> 5] >> (x & 31)) & 1u) sel += pa[(size_t)x];
             sel = std::min(1.0, sel);
             r.table_off = tpos[q] - q * (int64_t)sizeof(FilterRecord);
         } else {
@@ -359,8 +390,7 @@ static jag_status run_encode(const Index &ix, const jag_filter *F, int64_t nq, c
                              int64_t pool_len, FilterRecord *out, unsigned char *tab_base,
                              const int64_t *tpos)
 {
-    // large batches are encoded by several host threads (the range
-    // selectivity estimate is two binary searches over the sorted scalars)
+    // large batches are encoded by several host threads
     constexpr int64_t kPerThread = 2048;
     const int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()),
                                            std::min<int64_t>(16, nq / kPerThread));

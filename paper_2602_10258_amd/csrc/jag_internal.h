@@ -53,6 +53,11 @@ struct Predictor {
     float rho = 0.f;
 };
 
+// Pinned host buffers that jag_search_batch stages encoded filters in
+// (search.hip); each is reused once the copy out of it has completed.
+struct StagingRing;
+void free_staging(StagingRing *r);
+
 struct Index {
     int64_t n = 0;
     int32_t d = 0, R = 0, entry = 0, store = JAG_STORE_F32;
@@ -67,6 +72,12 @@ struct Index {
     std::vector<int64_t> loff;
     std::vector<int32_t> lab;
     std::vector<int32_t> scalar_sorted;
+    // rank index over scalar_sorted: the scalars of bucket b, the values in
+    // [scal_min + (b << scal_shift), scal_min + ((b + 1) << scal_shift)),
+    // sit at positions [scal_cum[b], scal_cum[b + 1]) (at most 2^16 buckets)
+    std::vector<int64_t> scal_cum;
+    int64_t scal_min = 0, scal_max = 0;
+    int32_t scal_shift = 0;
     std::vector<int64_t> label_count;
     // device memory
     int device = 0;
@@ -81,7 +92,12 @@ struct Index {
     uint16_t *d_lab = nullptr;
     int64_t device_bytes = 0;
     Predictor pred;
+    StagingRing *staging = nullptr;
 };
+
+// Number of items whose scalar is below v (exact; the rank index narrows
+// the binary search to one bucket).
+int64_t scalar_rank_below(const Index &ix, int64_t v);
 
 // Row stride of a store: rows are padded to a multiple of 64 bytes; an FP8
 // row keeps its FP32 scale in its last 4 bytes.

@@ -24,12 +24,26 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "jag_internal.h"
 
 namespace jag {
+
+// Pinned host buffers of jag_search_batch (see the staging section below).
+struct StagingBuf {
+    unsigned char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t copied = nullptr;  // recorded after the copy out of `host`
+    bool filling = false;         // a caller is encoding into it
+};
+
+struct StagingRing {
+    std::mutex mu;
+    std::vector<StagingBuf> bufs;
+};
 
 namespace {
 
@@ -1164,6 +1178,7 @@ jag_status upload_index(Index &ix)
     const int64_t n = ix.n;
     const int d = ix.d;
     jag_status st;
+    if (!ix.staging) ix.staging = new StagingRing();
     // adjacency rows with the neighbours' attributes inlined:
     //   [R ids][R scalars, if any][R x W/2 label words, if any], each part
     //   starting on a 16-byte boundary; -1 / 0 / 0xFFFF padding
@@ -1264,6 +1279,8 @@ jag_status upload_index(Index &ix)
 
 void free_device(Index &ix)
 {
+    free_staging(ix.staging);
+    ix.staging = nullptr;
     auto f = [](void *p) {
         if (p) (void)hipFree(p);
     };
@@ -1470,13 +1487,13 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     // its state (list and counters), order the chunk by predicted
     // beam, widest first, then resume every search in that order; the
     // scratch is stream-ordered memory from the default pool
-    keep_pool_reserved(ix.device);
     const int64_t stride = state_words(a.Lcap);
     const int64_t per_q = (stride + 2) * (int64_t)sizeof(int32_t);
+    keep_pool_reserved(ix.device);
     const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
-    int32_t *scratch = nullptr;
-    HIPCHK(hipMallocAsync((void **)&scratch, (size_t)(chunk * per_q), sm));
-    int32_t *perm = scratch + chunk * stride;
+    int32_t *saved = nullptr;
+    HIPCHK(hipMallocAsync((void **)&saved, (size_t)(chunk * per_q), sm));
+    int32_t *perm = saved + chunk * stride;
     int32_t *okey = perm + chunk;
     hipError_t e = hipSuccess;
     for (int64_t c0 = 0; c0 < nq && e == hipSuccess; c0 += chunk) {
@@ -1488,7 +1505,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         b.dists = a.dists + c0 * k;
         b.count = a.count + c0;
         b.stats = a.stats ? a.stats + c0 * 4 : nullptr;
-        b.state = scratch;
+        b.state = saved;
         b.state_stride = stride;
         b.order_key = okey;
         SearchArgs b3 = b;
@@ -1505,7 +1522,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         hipLaunchKernelGGL(fn, dim3((unsigned)nc), dim3(64), lds, sm, b);
         e = hipGetLastError();
     }
-    hipError_t ef = hipFreeAsync(scratch, sm);
+    hipError_t ef = hipFreeAsync(saved, sm);
     HIPCHK(e);
     HIPCHK(ef);
     return JAG_OK;
@@ -1582,6 +1599,90 @@ jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *recor
 
 }  // namespace jag
 
+// ---------------------------------------------------------------- staging
+// jag_search_batch encodes host filters into pinned host memory and copies
+// them to the device asynchronously; an event recorded after the copy says
+// when a buffer may be filled again, so the call never waits for the stream.
+namespace jag {
+
+constexpr size_t kStagingMax = 8;  // buffers per index; beyond that a caller waits
+
+void free_staging(StagingRing *r)
+{
+    if (!r) return;
+    for (auto &b : r->bufs) {
+        if (b.copied) {
+            (void)hipEventSynchronize(b.copied);
+            (void)hipEventDestroy(b.copied);
+        }
+        if (b.host) (void)hipHostFree(b.host);
+    }
+    delete r;
+}
+
+// A pinned buffer of at least `bytes` that no pending copy reads: a free one,
+// a new one while the ring is short, else the least recently filled one once
+// its copy has completed.  Returns its slot, or -1 with the error set.
+static int staging_acquire(StagingRing *r, size_t bytes)
+{
+    int pick = -1;
+    {
+        std::lock_guard<std::mutex> g(r->mu);
+        for (size_t i = 0; i < r->bufs.size() && pick < 0; i++) {
+            StagingBuf &b = r->bufs[i];
+            if (!b.filling && (!b.copied || hipEventQuery(b.copied) == hipSuccess)) pick = (int)i;
+        }
+        if (pick < 0 && r->bufs.size() < kStagingMax) {
+            r->bufs.emplace_back();
+            pick = (int)r->bufs.size() - 1;
+        }
+        if (pick < 0)
+            for (size_t i = 0; i < r->bufs.size() && pick < 0; i++)
+                if (!r->bufs[i].filling) pick = (int)i;
+        if (pick < 0) {
+            set_error("all %zu filter staging buffers are being filled by other calls", r->bufs.size());
+            return -1;
+        }
+        r->bufs[(size_t)pick].filling = true;
+    }
+    StagingBuf &b = r->bufs[(size_t)pick];
+    if (b.copied && hipEventSynchronize(b.copied) != hipSuccess) {
+        std::lock_guard<std::mutex> g(r->mu);
+        b.filling = false;
+        set_error("filter staging copy failed");
+        return -1;
+    }
+    if (!b.copied && hipEventCreateWithFlags(&b.copied, hipEventDisableTiming) != hipSuccess) {
+        std::lock_guard<std::mutex> g(r->mu);
+        b.filling = false;
+        set_error("event creation failed");
+        return -1;
+    }
+    if (b.cap < bytes) {
+        if (b.host) (void)hipHostFree(b.host);
+        b.host = nullptr;
+        b.cap = 0;
+        const size_t cap = std::max<size_t>((bytes + 4095) / 4096 * 4096, size_t(1) << 20);
+        if (hipHostMalloc((void **)&b.host, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            std::lock_guard<std::mutex> g(r->mu);
+            b.filling = false;
+            set_error("pinned staging allocation of %zu bytes failed", cap);
+            return -1;
+        }
+        b.cap = cap;
+    }
+    return pick;
+}
+
+static void staging_release(StagingRing *r, int slot)
+{
+    std::lock_guard<std::mutex> g(r->mu);
+    r->bufs[(size_t)slot].filling = false;
+}
+
+}  // namespace jag
+
 extern "C" jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t nq,
                                        const jag_filter *F, const int32_t *pool, int64_t pool_len,
                                        int32_t k, const jag_search_params *S, int32_t *ids,
@@ -1592,23 +1693,37 @@ extern "C" jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t n
         jag::set_error("null argument");
         return JAG_EINVAL;
     }
+    jag::Index &ix = idx->ix;
     int64_t bytes = 0;
     jag_status st = jag_encoded_bytes(idx, F, nq, pool, pool_len, &bytes);
     if (st != JAG_OK) return st;
-    std::vector<unsigned char> rec((size_t)bytes);
-    st = jag_encode_filters_sized(idx, F, nq, pool, pool_len, rec.data(), bytes);
-    if (st != JAG_OK) return st;
+    if (!ix.staging) {
+        jag::set_error("index has no staging ring");
+        return JAG_EDEVICE;
+    }
+    const int slot = jag::staging_acquire(ix.staging, (size_t)bytes);
+    if (slot < 0) return JAG_ENOMEM;
+    jag::StagingBuf &buf = ix.staging->bufs[(size_t)slot];
+    st = jag_encode_filters_sized(idx, F, nq, pool, pool_len, buf.host, bytes);
+    if (st != JAG_OK) {
+        jag::staging_release(ix.staging, slot);
+        return st;
+    }
     void *drec = nullptr;
     hipStream_t s = (hipStream_t)stream;
     if (hipMallocAsync(&drec, (size_t)bytes, s) != hipSuccess) {
+        (void)hipGetLastError();
+        jag::staging_release(ix.staging, slot);
         jag::set_error("device allocation for filter records failed");
         return JAG_ENOMEM;
     }
-    hipError_t e = hipMemcpyAsync(drec, rec.data(), (size_t)bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host staging buffer dies on return
-    if (e != hipSuccess) {
+    hipError_t e = hipMemcpyAsync(drec, buf.host, (size_t)bytes, hipMemcpyHostToDevice, s);
+    // the buffer may be filled again once this copy has run
+    hipError_t er = hipEventRecord(buf.copied, s);
+    jag::staging_release(ix.staging, slot);
+    if (e != hipSuccess || er != hipSuccess) {
         (void)hipFreeAsync(drec, s);
-        jag::set_error("filter upload failed: %s", hipGetErrorString(e));
+        jag::set_error("filter upload failed: %s", hipGetErrorString(e != hipSuccess ? e : er));
         return JAG_EDEVICE;
     }
     st = jag_search_encoded(idx, Q, nq, drec, k, S, ids, dists, count, stream);

@@ -18,6 +18,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -62,6 +64,7 @@ struct Slot {
     uint8_t *h_tab = nullptr, *d_tab = nullptr;
     size_t tab_cap = 0;
     std::vector<Request> batch;
+    int64_t batch_no = 0;  // 1-based count of the server's launches
     bool busy = false;
 };
 
@@ -86,6 +89,10 @@ struct jag_server {
     std::string error;
     std::thread worker;
     int64_t device_bytes = 0;
+    // Failure handling test hook: JAG_SERVER_TEST_FAIL_BATCH = b (b >= 1) makes
+    // the completion check of the server's b-th batch report a device error
+    // once that batch has finished normally (nothing faults on the device).
+    int64_t test_fail_batch = 0;
 };
 
 namespace {
@@ -178,6 +185,33 @@ bool launch(jag_server *S, Slot &s)
     return ok;
 }
 
+// Completion state of a slot's batch: hipSuccess, hipErrorNotReady, or the
+// error that ended it (the test hook turns success into a failure).
+hipError_t batch_status(const jag_server *S, const Slot &s)
+{
+    hipError_t e = hipEventQuery(s.event);
+    if (e == hipSuccess && S->test_fail_batch > 0 && s.batch_no == S->test_fail_batch)
+        e = hipErrorLaunchFailure;
+    return e;
+}
+
+// A batch ended in a device error: the server stops.  Its requests, and every
+// request still pending, never complete; poll and drain report JAG_EDEVICE,
+// submit refuses new requests, and stop waits for the other streams.
+void fail(jag_server *S, Slot &s, hipError_t e)
+{
+    std::lock_guard<std::mutex> g(S->mu);
+    char msg[256];
+    std::snprintf(msg, sizeof msg, "batch %lld of %zu requests failed on the device: %s",
+                  (long long)s.batch_no, s.batch.size(), hipGetErrorString(e));
+    S->error = msg;
+    S->inflight -= (int64_t)s.batch.size();
+    s.batch.clear();
+    s.busy = false;
+    S->stop = true;
+    S->cv_done.notify_all();
+}
+
 void finish(jag_server *S, Slot &s)
 {
     const int k = S->P.k;
@@ -206,11 +240,17 @@ void worker_loop(jag_server *S)
     const auto max_wait = std::chrono::microseconds(S->P.max_wait_us);
     for (;;) {
         bool progressed = false;
-        // 1. retire finished batches
+        // 1. retire finished batches; any status but "not ready" from a
+        // batch that did not succeed stops the server
         for (auto &s : S->slots) {
-            if (s.busy && hipEventQuery(s.event) == hipSuccess) {
+            if (!s.busy) continue;
+            const hipError_t e = batch_status(S, s);
+            if (e == hipSuccess) {
                 finish(S, s);
                 progressed = true;
+            } else if (e != hipErrorNotReady) {
+                fail(S, s, e);
+                return;
             }
         }
         // 2. admit pending requests onto idle streams
@@ -235,6 +275,7 @@ void worker_loop(jag_server *S)
                 S->max_inflight_seen = std::max(S->max_inflight_seen, S->inflight);
                 S->batches++;
                 S->batched_requests += want;
+                s.batch_no = S->batches;
                 s.busy = true;
             }
             if (!launch(S, s)) {
@@ -306,6 +347,7 @@ jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_serv
     S->resident = resident;
     S->max_inflight = P->max_inflight > 0 ? P->max_inflight : std::max<int64_t>(resident, P->max_batch);
     S->device_bytes = dev_bytes;
+    if (const char *fb = std::getenv("JAG_SERVER_TEST_FAIL_BATCH")) S->test_fail_batch = std::atoll(fb);
     S->slots.resize(P->n_streams);
     for (auto &s : S->slots) {
         if (!alloc_slot(s, P->max_batch, ix.d, P->k)) {

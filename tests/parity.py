@@ -35,6 +35,31 @@ def row_terms(store: int, d: int) -> tuple[int, int]:
     return ch * epc, G
 
 
+def lane_order(store: int, d: int) -> list[int]:
+    """The oracle's contract-mode order for the GPU's row layout: (G lanes,
+    elements per 16-byte chunk, chunks per lane) of the search store, then
+    of the FP32 rows the rerank reads (four lanes over 64-byte-padded rows,
+    or the store's own rows for an FP32 store)."""
+    eb = {0: 4, 1: 2, 2: 1}[store]
+    raw = eb * d + (4 if store == 2 else 0)
+    stride = (raw + 63) // 64 * 64
+    G = 4 if stride <= 512 else 16
+    if G == 16:
+        stride = (stride + 255) // 256 * 256
+    out = [G, 16 // eb, stride // (16 * G)]
+    f32_stride = stride if store == 0 else (4 * d + 63) // 64 * 64
+    return out + [4, 4, f32_stride // 64]
+
+
+def compare_strict(gpu_ids, gpu_d2, gpu_cnt, orc, what=""):
+    """Contract-mode oracle: every query's ids, count and FP32 distances equal."""
+    bad = [q for q in range(gpu_ids.shape[0])
+           if int(gpu_cnt[q]) != int(orc.count[q]) or not np.array_equal(gpu_ids[q], orc.ids[q])
+           or not np.array_equal(gpu_d2[q, :gpu_cnt[q]].astype(np.float64), orc.d2[q, :gpu_cnt[q]])]
+    assert not bad, f"{what}: {len(bad)} of {gpu_ids.shape[0]} queries differ, e.g. q={bad[0]} " \
+                    f"gpu={gpu_ids[bad[0]].tolist()} oracle={orc.ids[bad[0]].tolist()}"
+
+
 def tau_for(store: int, d: int, rerank_d: int | None = None) -> float:
     m, G = row_terms(store, d)
     eps = (m + 2 + math.log2(G)) * U

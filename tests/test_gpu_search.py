@@ -11,7 +11,7 @@ from paper_2602_10258_amd import jag
 from workloads import (FILTER_BOOLEAN, FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, encode_filters,
                        make_config)
 
-from .parity import compare, tau_for
+from .parity import compare, compare_strict, lane_order, tau_for
 
 pytestmark = pytest.mark.gpu
 
@@ -86,6 +86,9 @@ def test_all_filter_types_match_oracle(mixed_world, L):
                                _valid_fn(w, w.F, w.pool), f"mixed L={L}")
     _say(f"exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
     assert n_ex >= 0.8 * w.nq
+    orc_c = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, L, 10, contract=lane_order(0, w.d))
+    compare_strict(g["ids"], g["d2"], g["count"], orc_c, f"mixed L={L} (contract)")
+    assert np.array_equal(g["stats"][:, 0], orc_c.hops)
 
 
 @pytest.fixture(scope="module")
@@ -141,9 +144,13 @@ def test_wide_label_rows_match_oracle(store):
                                    _valid_fn(w, w.F, w.pool), f"wide labels L={L}")
         _say(f"L={L}: exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
         # longer trajectories over many near-equal distances leave more queries
-        # below the margin bound; most of those must still agree exactly
+        # below the margin bound; most of those must still agree exactly, and
+        # with the contract-mode oracle (the kernel's FP32 summation order)
+        # every query must
         assert n_ex >= 0.6 * w.nq
         assert n_ex + n_fl - n_fd >= 0.95 * w.nq
+        orc_c = O.search(Xs, adj, entry, A, w.Q, w.F, w.pool, L, 10, contract=lane_order(store, w.d))
+        compare_strict(g["ids"], g["d2"], g["count"], orc_c, f"wide labels L={L} (contract)")
 
 
 def test_quantizer_codes_bit_exact():

@@ -190,3 +190,34 @@ def test_table_filters_through_the_server():
         assert np.array_equal(ids, ref["ids"][q]) and c == ref["count"][q], q
     for i, (ids, d, c, lat) in alone:
         assert np.array_equal(ids, ref["ids"][i]) and c == ref["count"][i], i
+
+
+def test_failed_batch_stops_the_server_instead_of_hanging(mixed_world, monkeypatch):
+    """A batch whose completion check reports a device error (forced from the
+    host by the test hook; the device work itself finishes normally) stops the
+    server: drain and poll report JAG_EDEVICE, submit refuses new requests,
+    stop returns, and nothing waits forever."""
+    w, A, adj, entry = mixed_world
+    idx = _index(w, adj, entry)
+    monkeypatch.setenv("JAG_SERVER_TEST_FAIL_BATCH", "2")
+    s = jag.jag_server_start(idx, 10, jag.SearchParams(L=32), max_batch=4, n_streams=1, max_wait_us=0)
+    monkeypatch.delenv("JAG_SERVER_TEST_FAIL_BATCH")
+    try:
+        t = jag.jag_server_submit(s, w.Q[:40], w.F[:40], w.pool)
+        t0 = time.time()
+        with pytest.raises(jag.JagError) as e:
+            jag.jag_server_drain(s)
+        assert e.value.status == jag.JAG_EDEVICE
+        assert time.time() - t0 < 30
+        first = [jag.jag_server_poll(s, int(x)) for x in t[:4]]  # batch 1 completed
+        assert all(r is not None for r in first)
+        for x in t[4:8]:  # batch 2 failed
+            with pytest.raises(jag.JagError) as e:
+                jag.jag_server_poll(s, int(x))
+            assert e.value.status == jag.JAG_EDEVICE
+        with pytest.raises(jag.JagError) as e:
+            jag.jag_server_submit(s, w.Q[:1], w.F[:1], w.pool)
+        assert e.value.status == jag.JAG_EDEVICE
+    finally:
+        jag.jag_server_stop(s)
+    _say("failed batch reported, server stopped")

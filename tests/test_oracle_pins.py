@@ -241,3 +241,103 @@ def test_rerank_of_a_prefix_resorts_the_store_top_entries():
         np.testing.assert_allclose(r.d2[q, :len(want)], sorted(d2), rtol=1e-12)
         moved += want != ids
     assert moved >= Q.shape[0] // 2
+
+
+# ---------------------------------------------------------------- selectivity
+
+def _labels_world(sets, scal=None):
+    n = len(sets)
+    loff = np.zeros(n + 1, dtype=np.int64)
+    loff[1:] = np.cumsum([len(s) for s in sets])
+    lab = np.array([v for s in sets for v in s], dtype=np.int32)
+    return O.Attrs(n, scal, loff, lab)
+
+
+def test_selectivity_estimate_hand_worked():
+    """Items {0}, {0,1}, {1}, {}: each label held by half of them.  Label 0:
+    2/4 (a count); subset {0,1}: 1/2 * 1/2; (0 and 1) or not 0: 1/4 + 1/2 (the
+    clauses exclude each other); (0) or (1): 1 - 1/4; range [5, 7] over
+    scalars 1, 5, 7, 9: 2/4."""
+    A = _labels_world([[0], [0, 1], [1], []], scal=np.array([1, 5, 7, 9], np.int32))
+    F, pool = encode_filters([FILTER_LABEL, FILTER_SUBSET, FILTER_BOOLEAN, FILTER_BOOLEAN, FILTER_RANGE],
+                             [0, [0, 1], [[0, 1], [~0]], [[0], [1]], (5, 7)])
+    np.testing.assert_allclose(O.selectivity(A, F, pool), [0.5, 0.25, 0.75, 0.75, 0.5], rtol=1e-15)
+
+
+def test_selectivity_estimate_against_exact_counts_under_independent_labels():
+    """Labels drawn independently per item: the estimate is the probability a
+    random item passes, so the exact count (Pre-Filtering) must lie within a
+    few binomial standard deviations of n times the estimate; label and range
+    estimates are the exact fraction."""
+    rng = np.random.default_rng(12)
+    n = 100_000
+    p = np.array([0.5, 0.4, 0.3, 0.2, 0.1, 0.05, 0.6, 0.7])
+    held = rng.random((n, len(p))) < p
+    sets = [np.flatnonzero(r).tolist() for r in held]
+    scal = rng.integers(0, 1000, size=n).astype(np.int32)
+    A = _labels_world(sets, scal)
+    kinds = [FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_SUBSET, FILTER_BOOLEAN, FILTER_BOOLEAN,
+             FILTER_BOOLEAN, FILTER_SUBSET]
+    pays = [3, (100, 349), [0, 1], [0, 1, 2, 6], [[0, 1], [2]], [[0, ~1], [3]], [[~0], [1, 2], [5, ~6]],
+            [4, 5]]
+    F, pool = encode_filters(kinds, pays)
+    est = O.selectivity(A, F, pool)
+    X = np.zeros((n, 1), np.float32)
+    _, _, nv = O.bruteforce(X, A, np.zeros((len(kinds), 1), np.float32), F, pool, 1)
+    frac = nv / n
+    np.testing.assert_allclose(est[:2], frac[:2], rtol=1e-12)
+    sd = np.sqrt(est * (1 - est) / n)
+    assert np.all(np.abs(est - frac) <= 6 * sd + 1e-12), (est, frac)
+    # the estimate follows the true independent probabilities too
+    true = [p[0] * p[1], p[0] * p[1] * p[2] * p[6], p[0] * p[1] + p[2] - p[0] * p[1] * p[2],
+            p[0] * (1 - p[1]) + p[3] - p[0] * (1 - p[1]) * p[3]]
+    np.testing.assert_allclose(est[[2, 3, 4, 5]], true, rtol=0.05)
+
+
+def test_selectivity_estimate_assumes_independence():
+    """With label 1 held only together with label 0 the subset {0, 1} passes
+    whatever holds label 1, but the estimate multiplies the two frequencies."""
+    A = _labels_world([[0, 1], [0], [0], [2]])
+    F, pool = encode_filters([FILTER_SUBSET], [[0, 1]])
+    assert O.selectivity(A, F, pool)[0] == pytest.approx(0.75 * 0.25)
+
+
+# ---------------------------------------------------------------- contract order
+
+def test_contract_mode_search_agrees_with_fp64():
+    """The FP32 lane-order distances stay within the rounding bound of the FP64
+    ones: on a world of small integer coordinates every sum is exact, so the
+    two modes return the same ids and distances; on Gaussian data every query
+    whose FP64 margin clears the bound returns the same ids."""
+    from tests.parity import lane_order, tau_for
+    X, A, Q, F, pool, *_ = _tiny_world_for_contract()
+    n = X.shape[0]
+    adj = np.array([[(i + j) % n for j in range(1, 9)] for i in range(n)], dtype=np.int32)
+    Xi = np.round(X * 4).astype(np.float32)
+    Qi = np.round(Q * 4).astype(np.float32)
+    for store in (0, 1, 2):
+        con = lane_order(store, X.shape[1])
+        a = O.search(Xi, adj, 0, A, Qi, F, pool, 24, 10, rerank=Xi, rerank_mult=2, contract=con)
+        b = O.search(Xi, adj, 0, A, Qi, F, pool, 24, 10, rerank=Xi, rerank_mult=2)
+        assert np.array_equal(a.ids, b.ids) and np.array_equal(a.d2, b.d2)
+        c = O.search(X, adj, 0, A, Q, F, pool, 24, 10, contract=con)
+        e = O.search(X, adj, 0, A, Q, F, pool, 24, 10)
+        ok = e.margin >= tau_for(store, X.shape[1])
+        assert ok.mean() > 0.5 and np.array_equal(c.ids[ok], e.ids[ok])
+        np.testing.assert_allclose(c.d2[c.ids >= 0], e.d2[e.ids >= 0], rtol=1e-5)
+
+
+def _tiny_world_for_contract(seed=6, n=300, d=37):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    sets = [sorted(rng.choice(5, size=rng.integers(1, 3), replace=False).tolist()) for _ in range(n)]
+    loff = np.zeros(n + 1, dtype=np.int64)
+    loff[1:] = np.cumsum([len(s) for s in sets])
+    lab = np.array([v for s in sets for v in s], dtype=np.int32)
+    A = O.Attrs(n, rng.integers(0, 100, size=n).astype(np.int32), loff, lab)
+    kinds = [FILTER_LABEL, FILTER_RANGE, FILTER_SUBSET, FILTER_BOOLEAN] * 6
+    pays = [int(rng.integers(0, 5)) if t == FILTER_LABEL else (10, 80) if t == FILTER_RANGE
+            else [0, 2] if t == FILTER_SUBSET else [[1], [3, ~4]] for t in kinds]
+    F, pool = encode_filters(kinds, pays)
+    Q = rng.normal(size=(len(kinds), d)).astype(np.float32)
+    return X, A, Q, F, pool
