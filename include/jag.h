@@ -321,6 +321,29 @@ jag_status jag_search_encoded(jag_index *idx, const float *Q, int64_t nq, const 
                               int32_t k, const jag_search_params *S, int32_t *ids, float *dists,
                               int32_t *count, void *stream);
 
+/*
+ * jag_search_encoded for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as jag_search_encoded; it
+ * calls no hipMalloc, hipFree or allocating library routine.  The scratch
+ * that jag_search_encoded allocates per call -- the launch order of a batch
+ * of at least 4096 queries at a fixed beam (or single-pass learned), 8 bytes
+ * per query, and the saved states of a two-pass learned search -- lives
+ * instead in one fixed 32 MiB device array per GPU, held from the first call
+ * until the process ends.  Limits: a batch needing a launch order may hold
+ * at most 4,194,304 queries (EINVAL beyond); two-pass learned searches run
+ * in chunks of queries whose states fit (about 41,000 per chunk at a 64-entry
+ * list).  Every call on one GPU shares that array and leaves its contents
+ * behind (nothing in it needs clearing: each launch writes what it reads),
+ * so calls whose work overlaps on one GPU -- on different streams or host
+ * threads -- race and must be serialised by the caller.
+ * Errors: as jag_search_encoded, plus EINVAL for a batch beyond the limit
+ * and EDEVICE if the array's address cannot be obtained.
+ */
+jag_status jag_search_encoded_noalloc(jag_index *idx, const float *Q, int64_t nq, const void *records,
+                                      int32_t k, const jag_search_params *S, int32_t *ids, float *dists,
+                                      int32_t *count, void *stream);
+
 /* Convenience: encode host filters into a pinned staging buffer, copy them
  * to the device (stream-ordered allocation on `stream`) and run
  * jag_search_encoded; asynchronous on `stream` (the call does not wait for

@@ -162,7 +162,7 @@ jag_status upload_index(Index &ix);
 void free_device(Index &ix);
 jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
                          const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
-                         void *stream);
+                         void *stream, void *fixed_scratch = nullptr, int64_t fixed_bytes = 0);
 // Query wavefronts of this search the device can hold resident at once.
 jag_status search_capacity(Index &ix, int32_t k, const jag_search_params &S, int64_t *resident,
                            size_t *lds_per_query);

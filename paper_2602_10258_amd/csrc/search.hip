@@ -1439,9 +1439,12 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
     return JAG_OK;
 }
 
+// fixed_scratch (device, fixed_bytes long), when given, replaces the
+// stream-ordered allocations: the launch order of a large batch and the
+// saved states of a two-pass learned search (processed in chunks that fit).
 jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
                          const jag_search_params &S, int32_t *ids, float *dists, int32_t *count,
-                         void *stream)
+                         void *stream, void *fixed_scratch, int64_t fixed_bytes)
 {
     SearchArgs a;
     SearchFn fn = nullptr;
@@ -1450,12 +1453,24 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     if (st != JAG_OK) return st;
     if (nq == 0) return JAG_OK;
     hipStream_t sm = (hipStream_t)stream;
+    const bool fixed = fixed_scratch != nullptr;
     int32_t *order = nullptr;
     if (sel_ordered(S, nq)) {
-        keep_pool_reserved(ix.device);
-        if (hipMallocAsync((void **)&order, 2 * sizeof(int32_t) * (size_t)nq, sm) != hipSuccess) {
-            (void)hipGetLastError();  // no memory for the order: submission order below
-            order = nullptr;
+        const int64_t need = 2 * (int64_t)sizeof(int32_t) * nq;
+        if (fixed) {
+            if (need > fixed_bytes) {
+                set_error("a batch of %lld queries needs %lld bytes of scratch for its launch order; "
+                          "the fixed scratch holds %lld", (long long)nq, (long long)need,
+                          (long long)fixed_bytes);
+                return JAG_EINVAL;
+            }
+            order = static_cast<int32_t *>(fixed_scratch);
+        } else {
+            keep_pool_reserved(ix.device);
+            if (hipMallocAsync((void **)&order, (size_t)need, sm) != hipSuccess) {
+                (void)hipGetLastError();  // no memory for the order: submission order below
+                order = nullptr;
+            }
         }
     }
     if (order) {
@@ -1473,7 +1488,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
             hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, sm, b);
             e = hipGetLastError();
         }
-        hipError_t ef = hipFreeAsync(order, sm);
+        hipError_t ef = fixed ? hipSuccess : hipFreeAsync(order, sm);
         HIPCHK(e);
         HIPCHK(ef);
         return JAG_OK;
@@ -1489,10 +1504,21 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
     // scratch is stream-ordered memory from the default pool
     const int64_t stride = state_words(a.Lcap);
     const int64_t per_q = (stride + 2) * (int64_t)sizeof(int32_t);
-    keep_pool_reserved(ix.device);
-    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
     int32_t *saved = nullptr;
-    HIPCHK(hipMallocAsync((void **)&saved, (size_t)(chunk * per_q), sm));
+    int64_t chunk;
+    if (fixed) {
+        chunk = std::min<int64_t>(nq, fixed_bytes / per_q);
+        if (chunk < 1) {
+            set_error("one saved search state needs %lld bytes; the fixed scratch holds %lld",
+                      (long long)per_q, (long long)fixed_bytes);
+            return JAG_EINVAL;
+        }
+        saved = static_cast<int32_t *>(fixed_scratch);
+    } else {
+        keep_pool_reserved(ix.device);
+        chunk = std::max<int64_t>(1, std::min<int64_t>(nq, kStateBudget / per_q));
+        HIPCHK(hipMallocAsync((void **)&saved, (size_t)(chunk * per_q), sm));
+    }
     int32_t *perm = saved + chunk * stride;
     int32_t *okey = perm + chunk;
     hipError_t e = hipSuccess;
@@ -1522,7 +1548,7 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         hipLaunchKernelGGL(fn, dim3((unsigned)nc), dim3(64), lds, sm, b);
         e = hipGetLastError();
     }
-    hipError_t ef = hipFreeAsync(saved, sm);
+    hipError_t ef = fixed ? hipSuccess : hipFreeAsync(saved, sm);
     HIPCHK(e);
     HIPCHK(ef);
     return JAG_OK;
@@ -1598,6 +1624,71 @@ jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *recor
 }
 
 }  // namespace jag
+
+// ---------------------------------------------------------------- no-allocation search
+// jag_search_encoded_noalloc keeps its scratch (launch order, saved states of
+// a two-pass learned search) in this file-scope device array instead of
+// allocating it.  In host code `scratch` only names the symbol: its device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.  Every call on a device shares that device's copy.
+namespace jag {
+constexpr int64_t kNoAllocScratchBytes = int64_t(32) << 20;
+}
+static __device__ __align__(256) unsigned char scratch[jag::kNoAllocScratchBytes];
+
+namespace jag {
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[256];
+
+// Device address of this device's `scratch` (the current device).
+jag_status scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= 256) {
+        set_error("device %d out of range", dev);
+        return JAG_EDEVICE;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return JAG_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return JAG_OK;
+}
+}  // namespace
+}  // namespace jag
+
+extern "C" jag_status jag_search_encoded_noalloc(jag_index *idx, const float *Q, int64_t nq,
+                                                 const void *records, int32_t k,
+                                                 const jag_search_params *S, int32_t *ids, float *dists,
+                                                 int32_t *count, void *stream)
+{
+    if (!idx || !S || nq < 0 || (nq > 0 && (!Q || !records || !ids || !dists || !count))) {
+        jag::set_error("null argument");
+        return JAG_EINVAL;
+    }
+    if (nq == 0) return JAG_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        jag::set_error("no current device");
+        return JAG_EDEVICE;
+    }
+    if (dev != idx->ix.device) {
+        jag::set_error("index lives on device %d, current device is %d", idx->ix.device, dev);
+        return JAG_EINVAL;
+    }
+    void *p = nullptr;
+    jag_status st = jag::scratch_address(dev, &p);
+    if (st != JAG_OK) return st;
+    return jag::launch_search(idx->ix, Q, nq, records, k, *S, ids, dists, count, stream, p,
+                              jag::kNoAllocScratchBytes);
+}
 
 // ---------------------------------------------------------------- staging
 // jag_search_batch encodes host filters into pinned host memory and copies

@@ -95,6 +95,7 @@ def lib():
             "jag_encoded_bytes": ([P, P, i64, P, i64, P], i32),
             "jag_encode_filters_sized": ([P, P, i64, P, i64, P, i64], i32),
             "jag_search_encoded": ([P, P, i64, P, i32, P, P, P, P, P], i32),
+            "jag_search_encoded_noalloc": ([P, P, i64, P, i32, P, P, P, P, P], i32),
             "jag_search_batch": ([P, P, i64, P, P, i64, i32, P, P, P, P, P], i32),
             "jag_exact_knn": ([P, P, i64, P, i32, P, P, P, P], i32),
             "jag_set_predictor": ([P, P, i32, P, f32], i32),
@@ -114,7 +115,7 @@ def lib():
 def exported_symbols() -> list[str]:
     return ["jag_build", "jag_build_graph", "jag_build_from_graph", "jag_save", "jag_load", "jag_free", "jag_info",
             "jag_get_graph", "jag_get_store", "jag_encode_filters", "jag_encoded_bytes",
-            "jag_encode_filters_sized", "jag_search_encoded",
+            "jag_encode_filters_sized", "jag_search_encoded", "jag_search_encoded_noalloc",
             "jag_search_batch", "jag_exact_knn", "jag_set_predictor", "jag_train_predictor",
             "jag_predictor_grad", "jag_last_error", "jag_version", "jag_server_start",
             "jag_server_submit", "jag_server_poll", "jag_server_drain", "jag_server_stats_get",
@@ -324,6 +325,16 @@ def jag_search_encoded(idx: Index, Q, records, k: int, params: SearchParams, ids
     _check(lib().jag_search_encoded(idx.handle, _ptr(Q), Q.shape[0], _ptr(records), int(k),
                                     C.byref(sp), _ptr(ids), _ptr(dists), _ptr(count),
                                     _stream(stream)))
+
+
+def jag_search_encoded_noalloc(idx: Index, Q, records, k: int, params: SearchParams, ids, dists, count,
+                               stream=None):
+    """jag_search_encoded with its scratch in the library's fixed device array
+    (no device allocation; calls overlapping on one GPU race)."""
+    sp = params.c()
+    _check(lib().jag_search_encoded_noalloc(idx.handle, _ptr(Q), Q.shape[0], _ptr(records), int(k),
+                                            C.byref(sp), _ptr(ids), _ptr(dists), _ptr(count),
+                                            _stream(stream)))
 
 
 def jag_search_batch(idx: Index, Q, F, pool, k: int, params: SearchParams, ids, dists, count,
