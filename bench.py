@@ -1,22 +1,33 @@
-"""Benchmark: filtered QPS at recall@10 = 0.95 on one MI355X.
+"""Benchmark: filtered QPS at recall@10 = 0.95 per filter type on one MI355X.
 
-Default workload (range filters, the study's headline shape): 1,000,000
-vectors, d = 96, 256-cluster Gaussian mixture, one int32 attribute uniform
-over [0, 10^6); 10,000 range queries with log-uniform selectivity over
-[1e-4, 1]; k = 10; graph R = 64, thresholds {100%, 1%, 0} of the scalar.
+One leg per (workload, filter type), all in the default run:
+  range   -- 1,000,000 x 96, 256-cluster mixture, int32 attribute over
+             [0, 10^6), 10,000 ranges of log-uniform selectivity, R = 64
+             (the headline: timed steps, counters, the full CPU baseline);
+  label   -- 20,000 x 32, 8 uniform labels, 10,000 label queries; and the
+             serving shard, 1,250,000 x 100 with 1-5 Zipf labels of 1,000;
+  subset  -- 1,000,000 x 128, 1-10 Zipf(1.1) labels of 1,000, subsets of
+             1-3 labels (queries with at least k valid items);
+  boolean -- the same items, (a AND b) OR c over Zipf labels.
+Then the predictor at config-4 scale: 200,000 training traces of mixed
+label/range/subset queries over the 20,000 x 32 vectors, scored on 10,000
+held-out queries.
 
-Setup (untimed): build the Threshold-JAG (on the GPU by default; --build
-host or both), lay out FP32, BF16 and FP8 indexes (with FP32 copies) over
-the same graph, compute the exact answers with the CPU oracle (FP64), sweep
-the fixed beam L for each store, fit the beam predictor on a separate query
-set (GPU kernels), sweep its offset for learned + BF16 + FP32-rerank search.
-Each mode's point is the smallest sweep beam or offset reaching recall
->= 0.95 (grid points, then bisection between the bracketing ones); the
-timed steps run the learned + BF16 point over the whole query batch
-(the fastest fixed mode where the learned search misses 0.95), inputs
-resident in HBM.  One JSON line on stdout.
+Per leg (untimed set-up): build the Threshold-JAG on the GPU, lay out FP32
+and BF16 (+ FP32 copy) indexes over the same graph, compute the exact
+answers with the CPU oracle (FP64), sweep the fixed beam L of each store,
+fit the beam predictor on a separate query set of the same filter type,
+sweep its offset for learned + BF16 + FP32-rerank search.  Each mode's
+point is the smallest sweep beam or offset reaching recall >= 0.95 (grid
+points, then bisection between the bracketing ones).  The operating point
+(learned + BF16 where it reaches 0.95, else the fastest fixed mode) is
+timed with HIP events (kernel path, records on the device) and end to end
+through jag_search_batch (host filters); its roofline counts the bytes the
+method must move.  The headline's timed steps run its operating point over
+the whole query batch, inputs resident in HBM.  One JSON line on stdout.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config c2|c1|c3|c5|bool15]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--legs c2:range,...]
+                    [--config c1|c2|c3|c5|bool15] [--no-c4]
 """
 from __future__ import annotations
 
@@ -46,7 +57,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default=None,
+                    help="run only this workload's legs (default: every leg of --legs)")
+    ap.add_argument("--legs", default="c2:range,c1:label,c3:subset,c3:boolean,c5:label",
+                    help="workload:filter-type legs; the first is the headline (timed steps, "
+                         "counters, full CPU baseline)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the predictor evaluation at 200k traces")
+    ap.add_argument("--c4-train", type=int, default=200000)
+    ap.add_argument("--c4-heldout", type=int, default=10000)
+    ap.add_argument("--leg-cpu-seconds", type=float, default=3.0,
+                    help="CPU baseline time per non-headline leg")
     ap.add_argument("--n", type=int, default=None, help="override the number of vectors")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--ntrain", type=int, default=20000)
@@ -74,7 +94,8 @@ def parse():
                     help="drop queries with fewer valid items (default: k for the label-set "
                          "workloads c3 and c5, else 0)")
     ap.add_argument("--filter-type", type=int, default=None, choices=[0, 1, 2, 3, 4],
-                    help="keep only the queries of this filter type (0 label, 1 range, 2 subset, 3 Boolean)")
+                    help="profile mode: keep only the queries of this filter type "
+                         "(0 label, 1 range, 2 subset, 3 Boolean)")
     ap.add_argument("--build", default="device", choices=["device", "host", "both"],
                     help="where the graph is built (both: host and device, checked equal, both timed)")
     ap.add_argument("--R", type=int, default=0, help="out-degree bound of the graph (default: the workload's)")
@@ -345,6 +366,498 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+FILTER_CODES = {"label": 0, "range": 1, "subset": 2, "boolean": 3, "table": 4}
+STORE_NAMES = {0: "fp32", 1: "bf16 (+fp32 rerank)", 2: "fp8 e4m3 + row scale (+fp32 rerank)"}
+
+
+def attr_bytes(w, ftype: int) -> int:
+    """Attribute bytes one fresh neighbour costs the method: the int32 scalar
+    of a range filter, else the item's labels as uint16 (up to the
+    workload's largest label count)."""
+    if ftype == 1:
+        return 4
+    return 2 * int(np.max(np.diff(w.loff)))
+
+
+def row_bytes(d: int, store: int) -> int:
+    return d * {0: 4, 1: 2, 2: 1}[store] + (4 if store == 2 else 0)
+
+
+def rounded(r: dict) -> dict:
+    return {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
+
+
+class Config:
+    """One workload: its graph, FP32 and BF16 (+ FP32 copy) indexes over the
+    same graph, and the oracle's exact answers of its queries."""
+
+    def __init__(self, args, name, dev, types=None):
+        import torch
+        from oracle import oracle as O
+        from paper_2602_10258_amd import jag
+        from workloads import make_config
+        self.name = name
+        t0 = time.time()
+        n = args.n if args.n else (1_250_000 if name == "c5" else None)
+        # the serving shard's queries mix four filter types: draw enough that
+        # each type a leg needs keeps about 10,000
+        if args.nq:
+            nq = args.nq
+        elif name == "c5":
+            nq = 40000 // len(types) if types else 10000
+        else:
+            nq = 10000 if name == "c1" else None
+        w = make_config(name, n=n, nq=nq)
+        if args.R:
+            w = dataclasses.replace(w, R=args.R)
+        if types is not None:
+            keep = np.isin(w.F[:, 0], types)
+            w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
+        self.thr = parse_thresholds(args.thresholds) if args.thresholds else THRESHOLDS[w.name]
+        log(f"workload {w.name}: n={w.n} d={w.d} nq={w.nq} ({time.time() - t0:.1f}s)")
+        t1 = time.time()
+        cache = args.graph_cache and args.graph_cache.replace("{config}", name)
+        if cache and os.path.exists(cache):
+            z = np.load(cache)
+            self.adj, self.entry, self.build_times = z["adj"], int(z["entry"]), {"cached": 0.0}
+        else:
+            self.adj, self.entry, self.build_times = build_graph(args, w, self.thr)
+            if cache:
+                np.savez(cache, adj=self.adj, entry=self.entry)
+        self.build_s = time.time() - t1
+        log(f"graph of {name} ready in {self.build_s:.1f}s, mean degree {(self.adj >= 0).sum(1).mean():.1f}")
+        self.kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
+        self.ix32 = jag.jag_build_from_graph(w.X, self.adj, self.entry, store=jag.STORE_F32, **self.kw)
+        self.ix16 = jag.jag_build_from_graph(w.X, self.adj, self.entry, store=jag.STORE_BF16, keep_f32=True,
+                                             **self.kw)
+        self._ix8 = None
+        # ground truth: the oracle's exact filtered k-NN in FP64
+        t2 = time.time()
+        self.nthr = min(os.cpu_count() or 1, 16)
+        self.A = O.attrs_of(w)
+        gi, gd, nv = O.bruteforce(w.X, self.A, w.Q, w.F, w.pool, w.k, nthreads=self.nthr)
+        log(f"exact answers of {name} (oracle, {self.nthr} threads) in {time.time() - t2:.1f}s")
+        min_valid = args.min_valid if args.min_valid is not None else (w.k if name in ("c3", "c5") else 0)
+        keep = nv >= min_valid
+        if not keep.all():
+            # label-set workloads keep only queries with at least k valid items
+            log(f"keeping {int(keep.sum())} of {len(keep)} queries with >= {min_valid} valid items")
+            w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
+            gi, gd, nv = gi[keep], gd[keep], nv[keep]
+        self.w, self.gi, self.nv = w, gi, nv
+        self.dev = dev
+        self.torch = torch
+
+    def ix8(self):
+        from paper_2602_10258_amd import jag
+        if self._ix8 is None:
+            w = self.w
+            self._ix8 = jag.jag_build_from_graph(w.X, self.adj, self.entry, store=jag.STORE_FP8_E4M3,
+                                                 keep_f32=True, **self.kw)
+        return self._ix8
+
+    def describe(self) -> str:
+        w = self.w
+        return (f"{w.name}: {w.n} x {w.d} clustered vectors ({w.meta.get('thresholds')}), k={w.k}, R={w.R}")
+
+
+class Leg:
+    """The queries of one filter type of a workload, on the device, with their
+    exact answers; sweeps and timings of every search mode over them."""
+
+    def __init__(self, cfg: Config, ftype: int, timer):
+        from paper_2602_10258_amd import jag
+        torch = cfg.torch
+        sel = np.flatnonzero(cfg.w.F[:, 0] == ftype)
+        assert len(sel), f"no {FILTER_NAMES[ftype]} queries in {cfg.name}"
+        self.cfg, self.ftype, self.timer = cfg, ftype, timer
+        self.Q = np.ascontiguousarray(cfg.w.Q[sel])
+        self.F = np.ascontiguousarray(cfg.w.F[sel])
+        self.pool = cfg.w.pool
+        self.gi, self.nv = cfg.gi[sel], cfg.nv[sel]
+        self.nq, self.k = len(sel), cfg.w.k
+        dev = cfg.dev
+        self.Qd = torch.from_numpy(self.Q).to(dev)
+        self.rec = {id(cfg.ix32): torch.from_numpy(jag.jag_encode_filters(cfg.ix32, self.F, self.pool)).to(dev),
+                    id(cfg.ix16): torch.from_numpy(jag.jag_encode_filters(cfg.ix16, self.F, self.pool)).to(dev)}
+        self.ids = torch.empty((self.nq, self.k), dtype=torch.int32, device=dev)
+        self.d2 = torch.empty((self.nq, self.k), dtype=torch.float32, device=dev)
+        self.cnt = torch.empty((self.nq,), dtype=torch.int32, device=dev)
+        self.stats = torch.zeros((self.nq, 4), dtype=torch.int32, device=dev)
+        self.has_valid = self.nv > 0
+
+    def records(self, ix):
+        from paper_2602_10258_amd import jag
+        if id(ix) not in self.rec:
+            self.rec[id(ix)] = self.cfg.torch.from_numpy(jag.jag_encode_filters(ix, self.F, self.pool)).to(self.cfg.dev)
+        return self.rec[id(ix)]
+
+    def recall(self, ids_np) -> float:
+        hits = np.zeros(self.nq)
+        for q in range(self.nq):
+            den = min(self.k, int(self.nv[q]))
+            if den:
+                hits[q] = len(set(self.gi[q, :den].tolist()) & set(ids_np[q].tolist())) / den
+        return float(hits[self.has_valid].mean())
+
+    def search(self, ix, sp):
+        from paper_2602_10258_amd import jag
+        jag.jag_search_encoded(ix, self.Qd, self.records(ix), self.k, sp, self.ids, self.d2, self.cnt)
+
+    def point(self, ix, sp) -> dict:
+        from paper_2602_10258_amd import jag
+        ms = self.timer.run(lambda: self.search(ix, sp), reps=7, warm=1)
+        self.search(ix, jag.SearchParams(**{**sp.__dict__, "stats": self.stats}))
+        self.cfg.torch.cuda.synchronize()
+        st = self.stats.cpu().numpy()
+        return dict(ms=ms, qps=self.nq / (ms / 1e3), recall=self.recall(self.ids.cpu().numpy()),
+                    hops=float(st[:, 0].mean()), ndist=float(st[:, 1].mean()), nattr=float(st[:, 2].mean()),
+                    lhat=float(st[:, 3].mean()))
+
+    def fixed_sweep(self, ix, label, rerank_mult=0, beams=None):
+        from paper_2602_10258_amd import jag
+        curve = []
+        for L in beams or LADDER_FIXED:
+            r = self.point(ix, jag.SearchParams(L=L, rerank_mult=rerank_mult))
+            r["L"] = L
+            curve.append(r)
+            log(f"{self.tag()} {label} L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f} hops={r['hops']:.1f}")
+            if r["recall"] >= 0.99:
+                break
+        # bisect the integer beams between the last grid point below recall
+        # 0.95 and the first at or above it: the measured point is the
+        # smallest beam reaching 0.95, not the next grid beam
+        j = next((i for i, r in enumerate(curve) if r["recall"] >= 0.95), None)
+        if j:
+            lo, hi = curve[j - 1]["L"], curve[j]["L"]
+            while hi - lo > 1:
+                mid = (lo + hi) // 2
+                r = self.point(ix, jag.SearchParams(L=mid, rerank_mult=rerank_mult))
+                r["L"] = mid
+                curve.append(r)
+                log(f"{self.tag()}   refine L={mid:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
+                lo, hi = (lo, mid) if r["recall"] >= 0.95 else (mid, hi)
+            curve.sort(key=lambda r: r["L"])
+        return curve
+
+    def learned_sweep(self, ntrain, L95, ladder_top=None, dump=None):
+        """Fit the predictor on a separate query set of this filter type and
+        sweep its offset; the narrowest ladder whose sweep reaches 0.95."""
+        from paper_2602_10258_amd import jag
+        from paper_2602_10258_amd import predictor as pred
+        from workloads.gen import extra_queries
+        cfg = self.cfg
+        t3 = time.time()
+        Qt, Ft, pt = extra_queries(cfg.w, ntrain * (2 if cfg.name == "c3" else 4 if cfg.name == "c5" else 1),
+                                   qseed=1000)
+        keep = Ft[:, 0] == self.ftype
+        Qt, Ft = np.ascontiguousarray(Qt[keep][:ntrain]), np.ascontiguousarray(Ft[keep][:ntrain])
+        learned, lad, rep = [], None, None
+        for top in ladder_tops(L95, ladder_top):
+            lad = learned_ladder(L95, top)
+            log(f"{self.tag()} learned ladder {lad.tolist()}")
+            P, rho, rep = pred.fit(cfg.ix16, Qt, Ft, pt, k=self.k, exact_idx=cfg.ix32, rerank_mult=4, dump=dump,
+                                   ladder=lad)
+            log(f"{self.tag()} predictor fitted on {rep.n_train} traces in {time.time() - t3:.1f}s: loss "
+                f"{rep.loss_first:.3f} -> {rep.loss_last:.3f}, rho={rho:.2f}, unreachable={rep.unreachable}")
+            learned = []
+            for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 6.0]:
+                r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=delta, rerank_mult=4))
+                r["delta"] = delta
+                learned.append(r)
+                log(f"{self.tag()} learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} qps={r['qps']:.0f} "
+                    f"mean Lhat={r['lhat']:.1f}")
+                if r["recall"] >= 0.995 or (r["recall"] >= 0.95 and delta >= 1.0):
+                    break
+            if any(r["recall"] >= 0.95 for r in learned):
+                break
+        # bisect the offset between the last point below 0.95 and the first at
+        # or above it (four halvings; midpoints rounded to 4 decimals)
+        j = next((i for i, r in enumerate(learned) if r["recall"] >= 0.95), None)
+        if j:
+            lo, hi = learned[j - 1]["delta"], learned[j]["delta"]
+            for _ in range(4):
+                mid = round((lo + hi) / 2, 4)
+                r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=mid, rerank_mult=4))
+                r["delta"] = mid
+                learned.append(r)
+                log(f"{self.tag()}   refine delta={mid:+.4f} recall={r['recall']:.4f} qps={r['qps']:.0f}")
+                lo, hi = (lo, mid) if r["recall"] >= 0.95 else (mid, hi)
+            learned.sort(key=lambda r: r["delta"])
+        return learned, lad, rep
+
+    def tag(self):
+        return f"[{self.cfg.name}:{FILTER_NAMES[self.ftype]}]"
+
+    def alg_bytes(self, st, store, rerank) -> float:
+        """Sum over the batch of the bytes the method must move per query:
+        per expansion the R neighbour ids, an attribute per fresh neighbour and
+        a row per distance, plus the query, its record, the outputs and the
+        rerank rows."""
+        w = self.cfg.w
+        per_q = (st[:, 0] * 4 * w.R + st[:, 2] * attr_bytes(w, self.ftype) + st[:, 1] * row_bytes(w.d, store)
+                 + 4 * w.d + 128 + 8 * self.k + 4)
+        if rerank:
+            per_q = per_q + 4 * self.k * 4 * w.d
+        return float(per_q.sum())
+
+    def op_measure(self, ix, sp, store, rerank, reps=7):
+        """Kernel time (median of HIP-event launches), roofline, and the end-to-end
+        rate from host filters (jag_search_batch: encoding, pinned staging and the
+        record upload included; query vectors and outputs on the device)."""
+        from paper_2602_10258_amd import jag
+        torch = self.cfg.torch
+        kern_ms = self.timer.run(lambda: self.search(ix, sp), reps=reps, warm=2)
+        self.search(ix, jag.SearchParams(**{**sp.__dict__, "stats": self.stats}))
+        torch.cuda.synchronize()
+        st = self.stats.cpu().numpy().astype(np.int64)
+        alg = self.alg_bytes(st, store, rerank)
+        achieved = alg / (kern_ms / 1e3) / 1e9
+
+        def host():
+            jag.jag_search_batch(ix, self.Qd, self.F, self.pool, self.k, sp, self.ids, self.d2, self.cnt)
+        host()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            host()
+        torch.cuda.synchronize()
+        e2e = self.nq * reps / (time.perf_counter() - t)
+        return dict(kernel_ms=round(kern_ms, 4), kernel_qps=round(self.nq / (kern_ms / 1e3), 1),
+                    end_to_end_qps=round(e2e, 1),
+                    roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": round(achieved / PEAK_HBM_GBS, 4)},
+                    alg_bytes_per_query=round(alg / self.nq, 1), mean_expansions=round(float(st[:, 0].mean()), 2),
+                    mean_distance_computations=round(float(st[:, 1].mean()), 2),
+                    mean_attribute_evaluations=round(float(st[:, 2].mean()), 2))
+
+    def cpu(self, L, seconds, sample):
+        """The oracle (FP64, plain FP32 fixed beam L) on the machine's host cores over
+        whole passes of a bounded sample of these queries."""
+        from oracle import oracle as O
+        cfg = self.cfg
+        m = min(sample, self.nq)
+        reps, cs = 0, 0.0
+        while reps == 0 or cs < seconds:
+            t4 = time.time()
+            O.search(cfg.w.X, cfg.adj, cfg.entry, cfg.A, self.Q[:m], self.F[:m], self.pool, L, self.k,
+                     nthreads=cfg.nthr)
+            cs += time.time() - t4
+            reps += 1
+        return {"value": round(reps * m / cs, 1), "unit": "queries/s", "cores": cfg.nthr, "kind": "oracle",
+                "sample": f"{m} of the {self.nq} {FILTER_NAMES[self.ftype]} queries of {cfg.name}, {reps} passes, "
+                          f"plain FP32 fixed beam L={L}, FP64 distances, {cs:.1f}s"}
+
+
+def at95(curve):
+    """The first sweep point (smallest beam or offset) at or above recall 0.95
+    (deterministic, where the fastest of several such points is noise), and
+    the QPS interpolated at 0.95 in (recall, log QPS)."""
+    ok = [r for r in curve if r["recall"] >= 0.95]
+    best = ok[0] if ok else None
+    interp = None
+    srt = sorted(curve, key=lambda r: r["recall"])
+    for a, b in zip(srt, srt[1:]):
+        if a["recall"] < 0.95 <= b["recall"]:
+            f = (0.95 - a["recall"]) / (b["recall"] - a["recall"])
+            interp = math.exp(math.log(a["qps"]) + f * (math.log(b["qps"]) - math.log(a["qps"])))
+    return best, interp
+
+
+def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
+    """Every mode of one filter type: FP32 fixed, BF16 + rerank fixed, (FP8 +
+    rerank fixed on the headline), learned + BF16 + rerank; the operating point
+    and its measurements."""
+    from paper_2602_10258_amd import jag
+    leg = Leg(cfg, ftype, timer)
+    log(f"{leg.tag()} {leg.nq} queries")
+    fixed = leg.fixed_sweep(cfg.ix32, "fp32")
+    fixed16 = leg.fixed_sweep(cfg.ix16, "bf16+rerank", rerank_mult=4)
+    L95 = next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None)
+    fixed8 = []
+    if headline and L95 is not None:
+        fixed8 = leg.fixed_sweep(cfg.ix8(), "fp8+rerank", rerank_mult=4,
+                                 beams=[L for L in LADDER_FIXED if L95 / 2 <= L <= 2 * L95])
+    learned, lad, rep = ([], None, None) if args.only_fixed else leg.learned_sweep(
+        args.ntrain, L95, args.ladder_top, args.dump_traces if headline else None)
+    best_f, interp_f = at95(fixed)
+    best_16, interp_16 = at95(fixed16)
+    best_8, interp_8 = at95(fixed8) if fixed8 else (None, None)
+    best_l, interp_l = at95(learned) if learned else (None, None)
+    cands = []
+    if best_l:
+        cands.append(("learned+bf16+rerank", cfg.ix16, jag.SearchParams(L=leg.k, learned=1, delta=best_l["delta"],
+                                                                        rerank_mult=4), 1, True, best_l))
+    if best_16:
+        cands.append(("bf16+rerank-fixed", cfg.ix16, jag.SearchParams(L=best_16["L"], rerank_mult=4), 1, True,
+                      best_16))
+    if best_f:
+        cands.append(("fp32-fixed", cfg.ix32, jag.SearchParams(L=best_f["L"]), 0, False, best_f))
+    if best_8:
+        cands.append(("fp8+rerank-fixed", cfg.ix8(), jag.SearchParams(L=best_8["L"], rerank_mult=4), 2, True, best_8))
+    out = {"workload": f"{FILTER_NAMES[ftype]} filters on {cfg.describe()}", "queries": leg.nq,
+           "qps_at_095": {
+               "fp32_fixed": best_f and round(best_f["qps"], 1), "fp32_fixed_L": best_f and best_f["L"],
+               "fp32_fixed_interp": interp_f and round(interp_f, 1),
+               "bf16_rerank_fixed": best_16 and round(best_16["qps"], 1), "bf16_rerank_fixed_L": best_16 and best_16["L"],
+               "bf16_rerank_fixed_interp": interp_16 and round(interp_16, 1),
+               "fp8_rerank_fixed": best_8 and round(best_8["qps"], 1), "fp8_rerank_fixed_L": best_8 and best_8["L"],
+               "learned_bf16_rerank": best_l and round(best_l["qps"], 1),
+               "learned_bf16_rerank_interp": interp_l and round(interp_l, 1),
+               "learned_delta": best_l and best_l["delta"], "learned_mean_beam": best_l and round(best_l["lhat"], 2)},
+           "learned_over_fp32_fixed": (best_l and best_f and round(best_l["qps"] / best_f["qps"], 4)) or None,
+           "learned_over_bf16_fixed": (best_l and best_16 and round(best_l["qps"] / best_16["qps"], 4)) or None,
+           "learned_ladder": None if lad is None else lad.tolist(),
+           "predictor": rep and rep.__dict__,
+           "graph_build_seconds": cfg.build_times,
+           "sweeps": {"fp32_fixed": [rounded(r) for r in fixed], "bf16_rerank_fixed": [rounded(r) for r in fixed16],
+                      "fp8_rerank_fixed": [rounded(r) for r in fixed8], "learned": [rounded(r) for r in learned]}}
+    if not cands:
+        top = max(fixed + fixed16 + learned, key=lambda r: r["recall"])
+        out["note"] = "no configuration reached recall@10 = 0.95"
+        out["best_recall"] = rounded(top)
+        return out, None
+    # the metric's configuration is the learned beam with the BF16 store; the
+    # fastest fixed mode stands in only where the learned search misses 0.95
+    op = cands[0] if best_l else max(cands, key=lambda c: c[5]["qps"])
+    mode, ix, sp, store, rerank, pt = op
+    name = f"{mode} L={sp.L}" if not sp.learned else f"{mode} delta={sp.delta:g}"
+    log(f"{leg.tag()} operating point: {name} ({rounded(pt)})")
+    out["operating_point"] = name
+    out["storage"] = STORE_NAMES[store]
+    out.update(leg.op_measure(ix, sp, store, rerank))
+    Lcpu = best_f["L"] if best_f else pt.get("L", 64)
+    if not args.no_cpu and not headline:
+        out["cpu_baseline"] = leg.cpu(Lcpu, args.leg_cpu_seconds, 2000)
+    return out, dict(leg=leg, mode=mode, ix=ix, sp=sp, store=store, rerank=rerank, point=pt, name=name, Lcpu=Lcpu)
+
+
+def predictor_eval(args, dev, timer):
+    """Config 4: the predictor trained on 200,000 traces of mixed label, range
+    and subset queries over the config-1 data, scored on 10,000 held-out
+    queries (mean squared error of the ladder index, and QPS at recall 0.95
+    against fixed beams on the same store)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2602_10258_amd import jag
+    from paper_2602_10258_amd import predictor as pred
+    from workloads import make_config
+    from workloads.gen import extra_queries
+    t0 = time.time()
+    w = make_config("c4", nq=args.c4_heldout)
+    thr = [(0, 1.0), (0, 0.01), (0, 0.0), (1, 0.01), (1, 0.0)]
+    adj, entry, _ = build_graph(argparse.Namespace(build="device"), w, thr)
+    kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
+    ix32 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_F32, **kw)
+    ix16 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_BF16, keep_f32=True, **kw)
+    Qt, Ft, pt = extra_queries(w, args.c4_train, qseed=4000)
+    lad = pred.LADDER
+    P, rho, rep = pred.fit(ix16, Qt, Ft, pt, k=w.k, exact_idx=ix32, rerank_mult=4, ladder=lad)
+    log(f"[c4] predictor fitted on {rep.n_train} traces: loss {rep.loss_first:.3f} -> {rep.loss_last:.3f}")
+
+    def score(Q, F, pool):
+        Qd, rec = pred._device_batch(ix16, Q, F, pool)
+        Qe, rece = pred._device_batch(ix32, Q, F, pool)
+        eids, ecnt = pred.exact_answers(ix32, Qe, rece, w.k)
+        feats, all_ids, hops = pred.traces(ix16, Qd, rec, w.k, lad, 4)
+        tgt, reached = pred.targets_from(all_ids, eids, ecnt, w.k)
+        ok = feats[:, 15] == 1.0
+        x = feats[ok].astype(np.float64)
+        W1, b1 = P[:1024].reshape(64, 16), P[1024:1088]
+        W2, b2 = P[1088:5184].reshape(64, 64), P[5184:5248]
+        y = np.maximum(np.maximum(x @ W1.T + b1, 0) @ W2.T + b2, 0) @ P[5248:5312] + P[5312]
+        t = tgt[ok].astype(np.float64)
+        mse = float(np.mean((y - t) ** 2))
+        return {"queries": int(ok.sum()), "mse_ladder_index": round(mse, 4),
+                "r2": round(1.0 - mse / max(float(np.var(t)), 1e-12), 4),
+                "unreachable": int((~reached).sum())}
+    train_score = score(Qt[:args.c4_heldout], Ft[:args.c4_heldout], pt)
+    held = score(w.Q, w.F, w.pool)
+    log(f"[c4] held-out: {held}; training sample: {train_score}")
+    # QPS at recall 0.95 on the held-out queries: fixed beams vs the learned beam
+    gi, gd, nv = O.bruteforce(w.X, O.attrs_of(w), w.Q, w.F, w.pool, w.k, nthreads=min(os.cpu_count() or 1, 16))
+    cfg = argparse.Namespace(name="c4", w=w, gi=gi, nv=nv, dev=dev, torch=torch, ix16=ix16, ix32=ix32)
+    out = {"workload": f"c4: mixed label/range/subset queries over the {w.n} x {w.d} config-1 vectors "
+                       f"(scalar{{100%,1%,0}}+labels{{1%,0}}), k={w.k}, R={w.R}",
+           "train_traces": rep.n_train, "train_loss_first": round(rep.loss_first, 4),
+           "train_loss_last": round(rep.loss_last, 4), "heldout": held, "train_sample": train_score}
+    legq = {}
+    for ft in (0, 1, 2):
+        leg = Leg(cfg, ft, timer)
+        f32 = leg.fixed_sweep(ix32, "fp32")
+        f16 = leg.fixed_sweep(ix16, "bf16+rerank", rerank_mult=4)
+        lr = []
+        for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]:
+            r = leg.point(ix16, jag.SearchParams(L=w.k, learned=1, delta=delta, rerank_mult=4))
+            r["delta"] = delta
+            lr.append(r)
+            if r["recall"] >= 0.95:
+                break
+        b32, b16, bl = at95(f32)[0], at95(f16)[0], at95(lr)[0]
+        legq[FILTER_NAMES[ft]] = {
+            "fp32_fixed": b32 and {"L": b32["L"], "qps": round(b32["qps"], 1), "expansions": round(b32["hops"], 2)},
+            "bf16_rerank_fixed": b16 and {"L": b16["L"], "qps": round(b16["qps"], 1),
+                                          "expansions": round(b16["hops"], 2)},
+            "learned_bf16_rerank": bl and {"delta": bl["delta"], "qps": round(bl["qps"], 1),
+                                           "expansions": round(bl["hops"], 2), "mean_beam": round(bl["lhat"], 2)}}
+        log(f"[c4:{FILTER_NAMES[ft]}] {legq[FILTER_NAMES[ft]]}")
+    out["heldout_qps_at_095"] = legq
+    out["seconds"] = round(time.time() - t0, 1)
+    return out
+
+
+def profile_main(args, dev):
+    """Only the operating point of one workload and filter type, for rocprofv3
+    (no sweeps, no ground truth)."""
+    from paper_2602_10258_amd import jag
+    from paper_2602_10258_amd import predictor as pred
+    from workloads import make_config
+    from workloads.gen import extra_queries
+    import torch
+    name = args.config or "c2"
+    w = make_config(name, n=args.n, nq=args.nq)
+    if args.R:
+        w = dataclasses.replace(w, R=args.R)
+    if args.filter_type is not None:
+        keep = w.F[:, 0] == args.filter_type
+        w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
+    k = w.k
+    adj, entry, _ = build_graph(args, w, parse_thresholds(args.thresholds) if args.thresholds else THRESHOLDS[w.name])
+    kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
+    store = {"fp32-fixed": jag.STORE_F32, "bf16+rerank-fixed": jag.STORE_BF16,
+             "fp8+rerank-fixed": jag.STORE_FP8_E4M3, "learned+bf16+rerank": jag.STORE_BF16}[args.op_mode]
+    ix = jag.jag_build_from_graph(w.X, adj, entry, store=store, keep_f32=store != jag.STORE_F32, **kw)
+    if args.op_mode == "learned+bf16+rerank":
+        ix32 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_F32, **kw)
+        Qt, Ft, pt = extra_queries(w, args.ntrain * (2 if name == "c3" else 1), qseed=1000)
+        if args.filter_type is not None:
+            keep = Ft[:, 0] == args.filter_type
+            Qt, Ft = np.ascontiguousarray(Qt[keep][:args.ntrain]), np.ascontiguousarray(Ft[keep][:args.ntrain])
+        lad = (np.array([int(x) for x in args.ladder.split(",")], dtype=np.int32) if args.ladder
+               else learned_ladder(None))
+        pred.fit(ix, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4, ladder=lad)
+        sp = jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4)
+    else:
+        sp = jag.SearchParams(L=args.L, rerank_mult=0 if store == jag.STORE_F32 else 4)
+    Qd = torch.from_numpy(w.Q).to(dev)
+    rec = torch.from_numpy(jag.jag_encode_filters(ix, w.F, w.pool)).to(dev)
+    ids = torch.empty((w.nq, k), dtype=torch.int32, device=dev)
+    d2 = torch.empty((w.nq, k), dtype=torch.float32, device=dev)
+    cnt = torch.empty((w.nq,), dtype=torch.int32, device=dev)
+    for i in range(args.warmup + args.steps):
+        jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, d2, cnt)
+    torch.cuda.synchronize()
+    log(f"profiled {args.steps} steps of {args.op_mode} L={args.L} on {name} ({w.nq} queries)")
+    if args.calib_bytes:
+        # a plain device copy of known size, to scale the memory counters
+        src = torch.empty(args.calib_bytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copies of {args.calib_bytes} bytes done")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -354,291 +867,96 @@ def main():
     if args.serve:
         return serve_main(args)
     import torch
-    from paper_2602_10258_amd import jag
-    from paper_2602_10258_amd import predictor as pred
-    from workloads import make_config
-    from workloads.gen import extra_queries
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    w = make_config(args.config, n=args.n, nq=args.nq)
-    if args.R:
-        w = dataclasses.replace(w, R=args.R)
-    if args.filter_type is not None:
-        keep = w.F[:, 0] == args.filter_type
-        assert keep.any(), f"no queries of filter type {args.filter_type} in {w.name}"
-        w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
-    k = w.k
-    log(f"workload {w.name}: n={w.n} d={w.d} nq={w.nq} ({time.time() - t0:.1f}s)")
-
-    # ---- build the graph and lay out the two stores over it
-    thr_list = parse_thresholds(args.thresholds) if args.thresholds else THRESHOLDS[w.name]
-    t1 = time.time()
-    if args.graph_cache and os.path.exists(args.graph_cache):
-        z = np.load(args.graph_cache)
-        adj, entry = z["adj"], int(z["entry"])
-        build_times = {"cached": 0.0}
-        log(f"graph loaded from {args.graph_cache}")
-    else:
-        adj, entry, build_times = build_graph(args, w, thr_list)
-        if args.graph_cache:
-            np.savez(args.graph_cache, adj=adj, entry=entry)
-    build_s = time.time() - t1
-    log(f"graph built in {build_s:.1f}s, mean degree {(adj >= 0).sum(1).mean():.1f}")
+    if args.profile_op:
+        return profile_main(args, dev)
     if args.build_only:
+        from workloads import make_config
+        name = args.config or "c2"
+        w = make_config(name, n=args.n, nq=args.nq or 10)
+        if args.R:
+            w = dataclasses.replace(w, R=args.R)
+        thr = parse_thresholds(args.thresholds) if args.thresholds else THRESHOLDS[w.name]
+        adj, entry, times = build_graph(args, w, thr)
         print(json.dumps({"workload": w.name, "n": w.n, "d": w.d, "R": w.R, "L_build": 2 * w.R,
-                          "thresholds": [list(t) for t in thr_list],
-                          "graph_build_seconds": build_times,
+                          "thresholds": [list(t) for t in thr], "graph_build_seconds": times,
                           "mean_degree": round(float((adj >= 0).sum(1).mean()), 2)}))
         return
-    kw = dict(scalar=w.scalar, label_off=w.loff, labels=w.lab, vocab=w.vocab)
-    ix32 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_F32, **kw)
-    ix16 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_BF16, keep_f32=True, **kw)
-    rec32 = torch.from_numpy(jag.jag_encode_filters(ix32, w.F, w.pool)).to(dev)
-    rec16 = torch.from_numpy(jag.jag_encode_filters(ix16, w.F, w.pool)).to(dev)
-    Qd = torch.from_numpy(w.Q).to(dev)
-    nq = w.nq
-    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
-    d2 = torch.empty((nq, k), dtype=torch.float32, device=dev)
-    cnt = torch.empty((nq,), dtype=torch.int32, device=dev)
-    stats = torch.zeros((nq, 4), dtype=torch.int32, device=dev)
-
-    if args.profile_op:
-        # only the operating point, for rocprofv3 (no sweeps, no ground truth)
-        if args.op_mode == "fp32-fixed":
-            ix, rec, sp = ix32, rec32, jag.SearchParams(L=args.L)
-        elif args.op_mode == "bf16+rerank-fixed":
-            ix, rec, sp = ix16, rec16, jag.SearchParams(L=args.L, rerank_mult=4)
-        elif args.op_mode == "fp8+rerank-fixed":
-            ix = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_FP8_E4M3, keep_f32=True, **kw)
-            rec = torch.from_numpy(jag.jag_encode_filters(ix, w.F, w.pool)).to(dev)
-            sp = jag.SearchParams(L=args.L, rerank_mult=4)
-        else:
-            Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
-            lad = (np.array([int(x) for x in args.ladder.split(",")], dtype=np.int32) if args.ladder
-                   else learned_ladder(None))
-            pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4, ladder=lad)
-            ix, rec, sp = ix16, rec16, jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4)
-        for i in range(args.warmup + args.steps):
-            jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, d2, cnt)
-        torch.cuda.synchronize()
-        log(f"profiled {args.steps} steps of {args.op_mode} L={args.L}")
-        if args.calib_bytes:
-            # a plain device copy of known size, to scale the memory counters
-            src = torch.empty(args.calib_bytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-            dst = torch.empty_like(src)
-            for _ in range(3):
-                dst.copy_(src)
-            torch.cuda.synchronize()
-            log(f"calibration copies of {args.calib_bytes} bytes done")
-        return
-
-    # ---- ground truth: the oracle's exact filtered k-NN in FP64
-    from oracle import oracle as O
-    t2 = time.time()
-    nthr = min(os.cpu_count() or 1, 16)
-    A = O.attrs_of(w)
-    gi, gd, nv = O.bruteforce(w.X, A, w.Q, w.F, w.pool, k, nthreads=nthr)
-    log(f"exact answers (oracle, {nthr} threads) in {time.time() - t2:.1f}s")
-    min_valid = args.min_valid if args.min_valid is not None else (k if w.name in ("c3", "c5") else 0)
-    if min_valid > 0 and (nv < min_valid).any():
-        # label-set workloads keep only queries with at least k valid items
-        keep = nv >= min_valid
-        log(f"keeping {int(keep.sum())} of {len(keep)} queries with >= {min_valid} valid items")
-        w = dataclasses.replace(w, Q=np.ascontiguousarray(w.Q[keep]), F=np.ascontiguousarray(w.F[keep]))
-        gi, gd, nv = gi[keep], gd[keep], nv[keep]
-        rec32 = torch.from_numpy(jag.jag_encode_filters(ix32, w.F, w.pool)).to(dev)
-        rec16 = torch.from_numpy(jag.jag_encode_filters(ix16, w.F, w.pool)).to(dev)
-        Qd = torch.from_numpy(w.Q).to(dev)
-        nq = w.nq
-        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
-        d2 = torch.empty((nq, k), dtype=torch.float32, device=dev)
-        cnt = torch.empty((nq,), dtype=torch.int32, device=dev)
-        stats = torch.zeros((nq, 4), dtype=torch.int32, device=dev)
-    has_valid = nv > 0
-
-    def recall(ids_np):
-        hits = np.zeros(nq)
-        for q in range(nq):
-            den = min(k, int(nv[q]))
-            if den:
-                hits[q] = len(set(gi[q, :den].tolist()) & set(ids_np[q].tolist())) / den
-        return float(hits[has_valid].mean())
-
+    legs = [tuple(x.split(":")) for x in args.legs.split(",")]
+    if args.config:
+        legs = [l for l in legs if l[0] == args.config] or [(args.config, t) for t in
+                                                              {"c1": ["label"], "c2": ["range"],
+                                                               "c3": ["subset", "boolean"], "c4": [],
+                                                               "c5": ["label", "range", "subset", "boolean"],
+                                                               "bool15": ["table"]}[args.config]]
     timer = Timer()
+    configs, results = {}, {}
+    headline = {}
+    t_all = time.time()
+    for i, (cname, tname) in enumerate(legs):
+        if cname not in configs:
+            # one workload's graph and indexes at a time on the device
+            configs.clear()
+            configs[cname] = Config(args, cname, dev, [FILTER_CODES[t] for c, t in legs if c == cname])
+        out, op = run_leg(args, configs[cname], FILTER_CODES[tname], timer, headline=i == 0)
+        results[f"{tname}:{cname}"] = out
+        if i == 0:
+            headline = timed_steps(args, configs[cname], out, op)
+        log(f"leg {tname}:{cname} done at {time.time() - t_all:.0f}s")
+    configs.clear()
+    c4 = None
+    if not args.no_c4 and not args.config:
+        c4 = predictor_eval(args, dev, timer)
+    hout = results[f"{legs[0][1]}:{legs[0][0]}"]
+    op = headline.get("op")
+    learned_wins = {k_: (v.get("learned_over_bf16_fixed") or 0) > 1.0 for k_, v in results.items()}
+    summary = {k_: {"fp32_fixed": v["qps_at_095"]["fp32_fixed"], "bf16_rerank_fixed": v["qps_at_095"]["bf16_rerank_fixed"],
+                    "learned_bf16_rerank": v["qps_at_095"]["learned_bf16_rerank"],
+                    "learned_over_fp32_fixed": v.get("learned_over_fp32_fixed"),
+                    "learned_over_bf16_fixed": v.get("learned_over_bf16_fixed"),
+                    "roofline_frac": v.get("roofline", {}).get("frac"), "end_to_end_qps": v.get("end_to_end_qps"),
+                    "kernel_qps": v.get("kernel_qps")} for k_, v in results.items()}
+    out = {
+        "metric": METRIC, "value": headline.get("value"), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": headline.get("ms_per_step"),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if op and op["store"] == 1 else "fp8" if op and op["store"] == 2 else "f32",
+        "data": "synthetic",
+        "config": {"workload": hout["workload"], "filter_type": legs[0][1], "global_batch": hout["queries"],
+                   "mode": op and op["mode"], "recall_at_10": headline.get("recall"),
+                   "storage": op and STORE_NAMES[op["store"]], "accumulate": "fp32"},
+        "roofline": hout.get("roofline"),
+        "cpu_baseline": hout.get("cpu_baseline"),
+        "cpu_baseline_one_thread": headline.get("cpu1"),
+        "operating_point": hout.get("operating_point"),
+        "kernel_ms": headline.get("kernel_ms"),
+        "end_to_end_qps": hout.get("end_to_end_qps"),
+        "per_filter_type": summary,
+        "learned_beats_bf16_fixed": learned_wins,
+        "legs": results,
+        "predictor_c4": c4,
+        "seconds": round(time.time() - t_all, 1),
+    }
+    print(json.dumps(out, default=float), flush=True)
 
-    def point(ix, rec, sp):
-        def fn():
-            jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, d2, cnt)
-        ms = timer.run(fn, reps=7, warm=1)
-        sp2 = jag.SearchParams(**{**sp.__dict__, "stats": stats})
-        jag.jag_search_encoded(ix, Qd, rec, k, sp2, ids, d2, cnt)
-        torch.cuda.synchronize()
-        st = stats.cpu().numpy()
-        return dict(ms=ms, qps=nq / (ms / 1e3), recall=recall(ids.cpu().numpy()),
-                    hops=float(st[:, 0].mean()), ndist=float(st[:, 1].mean()),
-                    nattr=float(st[:, 2].mean()), lhat=float(st[:, 3].mean()))
 
-    def refine_fixed(curve, run):
-        # bisect the integer beams between the last grid point below recall
-        # 0.95 and the first at or above it, so that the measured point is
-        # the smallest beam reaching 0.95, not the next grid beam
-        j = next((i for i, r in enumerate(curve) if r["recall"] >= 0.95), None)
-        if not j:
-            return
-        lo, hi = curve[j - 1]["L"], curve[j]["L"]
-        while hi - lo > 1:
-            mid = (lo + hi) // 2
-            r = run(mid)
-            r["L"] = mid
-            curve.append(r)
-            log(f"  refine L={mid:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
-            lo, hi = (lo, mid) if r["recall"] >= 0.95 else (mid, hi)
-        curve.sort(key=lambda r: r["L"])
+def timed_steps(args, cfg, hout, op):
+    """The headline leg's operating point: `warmup` untimed steps, then `steps`
+    timed ones (HIP events on the search stream, wall clock around all of them),
+    the roofline of their kernel time, the committed counters when they match
+    this source, and the CPU baseline."""
+    import torch
+    if op is None:
+        return {}
+    leg, ix, sp = op["leg"], op["ix"], op["sp"]
 
-    # ---- plain FP32, fixed beam sweep
-    ladder_fixed = LADDER_FIXED
-    fixed = []
-    for L in ladder_fixed:
-        r = point(ix32, rec32, jag.SearchParams(L=L))
-        r["L"] = L
-        fixed.append(r)
-        log(f"fp32 L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f} hops={r['hops']:.1f}")
-        if r["recall"] >= 0.99:
-            break
-    refine_fixed(fixed, lambda L: point(ix32, rec32, jag.SearchParams(L=L)))
-    # ---- ablation: BF16 + FP32 rerank with a fixed beam (no predictor)
-    fixed16 = []
-    for L in ladder_fixed:
-        r = point(ix16, rec16, jag.SearchParams(L=L, rerank_mult=4))
-        r["L"] = L
-        fixed16.append(r)
-        log(f"bf16+rerank L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
-        if r["recall"] >= 0.99:
-            break
-    refine_fixed(fixed16, lambda L: point(ix16, rec16, jag.SearchParams(L=L, rerank_mult=4)))
-    # ---- ablation: FP8 E4M3 (per-row scale) + FP32 rerank, beams around BF16's 0.95 point
-    fixed8 = []
-    L95 = next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None)
-    if L95 is not None and not args.only_fixed:
-        ix8 = jag.jag_build_from_graph(w.X, adj, entry, store=jag.STORE_FP8_E4M3, keep_f32=True, **kw)
-        rec8 = torch.from_numpy(jag.jag_encode_filters(ix8, w.F, w.pool)).to(dev)
-        for L in [L for L in ladder_fixed if L95 / 2 <= L <= 2 * L95]:
-            r = point(ix8, rec8, jag.SearchParams(L=L, rerank_mult=4))
-            r["L"] = L
-            fixed8.append(r)
-            log(f"fp8+rerank L={L:4d} recall={r['recall']:.4f} qps={r['qps']:.0f}")
-        refine_fixed(fixed8, lambda L: point(ix8, rec8, jag.SearchParams(L=L, rerank_mult=4)))
-
-    # ---- learned + BF16 + FP32 rerank
-    learned = []
-    fit_rep = None
-    lad = None
-    if not args.only_fixed:
-        t3 = time.time()
-        Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
-        L95 = next((r["L"] for r in fixed16 if r["recall"] >= 0.95), None)
-        for top in ladder_tops(L95, args.ladder_top):
-            lad = learned_ladder(L95, top)
-            log(f"learned ladder {lad.tolist()}")
-            P, rho, fit_rep = pred.fit(ix16, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4,
-                                       dump=args.dump_traces, ladder=lad)
-            log(f"predictor fitted on {fit_rep.n_train} traces in {time.time() - t3:.1f}s: loss "
-                f"{fit_rep.loss_first:.3f} -> {fit_rep.loss_last:.3f}, rho={rho:.2f}, "
-                f"unreachable={fit_rep.unreachable}")
-            learned = []
-            for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0]:
-                r = point(ix16, rec16, jag.SearchParams(L=k, learned=1, delta=delta, rerank_mult=4))
-                r["delta"] = delta
-                learned.append(r)
-                log(f"learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} qps={r['qps']:.0f} "
-                    f"mean Lhat={r['lhat']:.1f}")
-                if r["recall"] >= 0.995:
-                    break
-            if any(r["recall"] >= 0.95 for r in learned):
-                break
-        # bisect the offset between the last sweep point below 0.95 and the
-        # first at or above it (four halvings of the grid step; midpoints
-        # rounded to 4 decimals, as the report and the profiles name them)
-        j = next((i for i, r in enumerate(learned) if r["recall"] >= 0.95), None)
-        if j:
-            lo, hi = learned[j - 1]["delta"], learned[j]["delta"]
-            for _ in range(4):
-                mid = round((lo + hi) / 2, 4)
-                r = point(ix16, rec16, jag.SearchParams(L=k, learned=1, delta=mid, rerank_mult=4))
-                r["delta"] = mid
-                learned.append(r)
-                log(f"  refine delta={mid:+.4f} recall={r['recall']:.4f} qps={r['qps']:.0f}")
-                lo, hi = (lo, mid) if r["recall"] >= 0.95 else (mid, hi)
-            learned.sort(key=lambda r: r["delta"])
-
-    def at95(curve):
-        # the first sweep point (smallest beam or offset) at or above 0.95:
-        # deterministic, where the fastest of several such points is noise
-        ok = [r for r in curve if r["recall"] >= 0.95]
-        best = ok[0] if ok else None
-        interp = None
-        srt = sorted(curve, key=lambda r: r["recall"])
-        for a, b in zip(srt, srt[1:]):
-            if a["recall"] < 0.95 <= b["recall"]:
-                f = (0.95 - a["recall"]) / (b["recall"] - a["recall"])
-                interp = math.exp(math.log(a["qps"]) + f * (math.log(b["qps"]) - math.log(a["qps"])))
-        return best, interp
-
-    best_f, interp_f = at95(fixed)
-    best_f16, interp_f16 = at95(fixed16)
-    best_f8, interp_f8 = at95(fixed8) if fixed8 else (None, None)
-    best_l, interp_l = at95(learned) if learned else (None, None)
-    cands = []
-    if best_l:
-        cands.append(dict(mode="learned+bf16+rerank", ix=ix16, rec=rec16,
-                          sp=jag.SearchParams(L=k, learned=1, delta=best_l["delta"], rerank_mult=4),
-                          store=jag.STORE_BF16, rerank=True, point=best_l))
-    if best_f16:
-        cands.append(dict(mode="bf16+rerank-fixed", ix=ix16, rec=rec16,
-                          sp=jag.SearchParams(L=best_f16["L"], rerank_mult=4),
-                          store=jag.STORE_BF16, rerank=True, point=best_f16))
-    if best_f:
-        cands.append(dict(mode="fp32-fixed", ix=ix32, rec=rec32, sp=jag.SearchParams(L=best_f["L"]),
-                          store=jag.STORE_F32, rerank=False, point=best_f))
-    if best_f8:
-        cands.append(dict(mode="fp8+rerank-fixed", ix=ix8, rec=rec8,
-                          sp=jag.SearchParams(L=best_f8["L"], rerank_mult=4),
-                          store=jag.STORE_FP8_E4M3, rerank=True, point=best_f8))
-    if not cands:
-        # nothing reaches the target: report the sweeps and the best recall seen
-        allp = [dict(r, mode=m) for m, rs in (("fp32-fixed", fixed), ("bf16+rerank-fixed", fixed16),
-                                              ("fp8+rerank-fixed", fixed8), ("learned+bf16+rerank", learned))
-                for r in rs]
-        top = max(allp, key=lambda r: r["recall"])
-        print(json.dumps({
-            "metric": METRIC, "value": None, "unit": "queries/s", "n_gpus": 1, "steps": 0,
-            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": f"{w.name}: {w.n} x {w.d} clustered vectors, {nq} queries "
-                                   f"({args.thresholds or w.meta.get('thresholds')}), k={k}, R={w.R}",
-                       "global_batch": nq, "filter_types": sorted({FILTER_NAMES[int(t)] for t in w.F[:, 0]})},
-            "note": "no configuration reached recall@10 = 0.95",
-            "best_recall": {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in top.items()},
-            "graph_build_seconds": build_times,
-            "sweeps": {"fixed": fixed, "bf16_rerank_fixed": fixed16, "fp8_rerank_fixed": fixed8,
-                       "learned": learned}}, default=float))
-        return
-    # the metric's configuration is the learned beam with the BF16 store;
-    # the fastest fixed-beam mode stands in only where it misses 0.95
-    op = cands[0] if best_l else max(cands, key=lambda c: c["point"]["qps"])
-    log(f"operating point: {op['mode']} ({op['point']})")
-
-    # ---- timed steps
     def step():
-        jag.jag_search_encoded(op["ix"], Qd, op["rec"], k, op["sp"], ids, d2, cnt)
-
+        leg.search(ix, sp)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t_start = time.perf_counter()
     for a, b in ev:
         a.record()
@@ -648,107 +966,32 @@ def main():
     wall = time.perf_counter() - t_start
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     ms_per_step = wall * 1e3 / args.steps
-    value = nq / (ms_per_step / 1e3)
-    rec_final = recall(ids.cpu().numpy())
-
-    # end to end from host filters: encoding, record upload and search
-    # (jag_search_batch), query vectors and outputs already on the device
-    def step_host():
-        jag.jag_search_batch(op["ix"], Qd, w.F, w.pool, k, op["sp"], ids, d2, cnt)
-    step_host()
+    rec = leg.recall(leg.ids.cpu().numpy())
+    leg.search(ix, _stats_params(sp, leg.stats))
     torch.cuda.synchronize()
-    t_h = time.perf_counter()
-    for _ in range(args.steps):
-        step_host()
-    torch.cuda.synchronize()
-    e2e_qps = nq * args.steps / (time.perf_counter() - t_h)
-
-    # ---- roofline: algorithmic bytes of one launch / its average duration
-    sp2 = jag.SearchParams(**{**op["sp"].__dict__, "stats": stats})
-    jag.jag_search_encoded(op["ix"], Qd, op["rec"], k, sp2, ids, d2, cnt)
-    torch.cuda.synchronize()
-    st = stats.cpu().numpy().astype(np.int64)
-    info = op["ix"].info()
-    row = w.d * {0: 4, 1: 2, 2: 1}[op["store"]] + (4 if op["store"] == 2 else 0)
-    attr = 4 if w.name == "c2" else 2 * max(1, info.label_width)
-    per_q = st[:, 0] * 4 * w.R + st[:, 2] * attr + st[:, 1] * row + 4 * w.d + 128 + 8 * k + 4
-    if op["rerank"]:
-        per_q = per_q + 4 * k * 4 * w.d
-    alg_bytes = float(per_q.sum())
-    achieved = alg_bytes / (kern_ms / 1e3) / 1e9
-    op_name = (f"{op['mode']} L={op['sp'].L}" if not op["sp"].learned
-               else f"{op['mode']} delta={op['sp'].delta:g}")
-    traffic = measured_traffic(w.name, op_name)
-
-    # ---- CPU baseline: the oracle, unchanged, on a bounded sample at the same beam
-    cpu = cpu1 = None
+    st = leg.stats.cpu().numpy().astype(np.int64)
+    achieved = leg.alg_bytes(st, op["store"], op["rerank"]) / (kern_ms / 1e3) / 1e9
+    hout["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(cfg.name, op["name"])}
+    out = {"op": {k_: op[k_] for k_ in ("mode", "store", "rerank", "name")},
+           "value": round(leg.nq / (ms_per_step / 1e3), 1), "ms_per_step": round(ms_per_step, 4),
+           "kernel_ms": round(kern_ms, 4), "recall": round(rec, 4)}
     if not args.no_cpu:
-        m = min(args.cpu_sample, nq)
-        Lcpu = op["point"].get("L", best_f["L"] if best_f else 64)
-        reps, cs = 0, 0.0
-        while reps == 0 or cs < args.cpu_seconds:  # whole passes over the sample, about cpu_seconds
-            t4 = time.time()
-            O.search(w.X, adj, entry, A, w.Q[:m], w.F[:m], w.pool, Lcpu, k, nthreads=nthr)
-            cs += time.time() - t4
-            reps += 1
-        cpu = {"value": reps * m / cs, "unit": "queries/s", "cores": nthr, "kind": "oracle",
-               "sample": f"first {m} of the {nq} queries, {reps} passes, plain FP32 fixed beam L={Lcpu}, "
-                         f"FP64 distances, {cs:.1f}s"}
-        # the same on one thread, over a tenth of the sample
-        m1 = max(1, m // 10)
+        from oracle import oracle as O
+        hout["cpu_baseline"] = leg.cpu(op["Lcpu"], args.cpu_seconds, args.cpu_sample)
+        m1 = max(1, min(args.cpu_sample, leg.nq) // 10)
         t4 = time.time()
-        O.search(w.X, adj, entry, A, w.Q[:m1], w.F[:m1], w.pool, Lcpu, k, nthreads=1)
-        cpu1 = {"value": round(m1 / (time.time() - t4), 1), "unit": "queries/s", "cores": 1,
-                "sample": f"first {m1} queries, same beam", "cpu_model": cpu_model()}
+        O.search(cfg.w.X, cfg.adj, cfg.entry, cfg.A, leg.Q[:m1], leg.F[:m1], leg.pool, op["Lcpu"], leg.k,
+                 nthreads=1)
+        out["cpu1"] = {"value": round(m1 / (time.time() - t4), 1), "unit": "queries/s", "cores": 1,
+                       "sample": f"first {m1} queries, same beam", "cpu_model": cpu_model()}
+    log(f"timed {args.steps} steps: {out['value']:.0f} queries/s, {out['ms_per_step']} ms per step")
+    return out
 
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.n} x {w.d} clustered vectors, {nq} queries "
-                               f"({args.thresholds or w.meta.get('thresholds')}), k={k}, R={w.R}",
-                   "global_batch": nq, "mode": op["mode"], "recall_at_10": round(rec_final, 4),
-                   "filter_types": sorted({FILTER_NAMES[int(t)] for t in w.F[:, 0]}),
-                   "storage": {jag.STORE_F32: "fp32", jag.STORE_BF16: "bf16 (+fp32 rerank)",
-                               jag.STORE_FP8_E4M3: "fp8 e4m3 + row scale (+fp32 rerank)"}[op["store"]]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic},
-        "operating_point": op_name,
-        "learned_ladder": None if lad is None else lad.tolist(),
-        "cpu_baseline": cpu,
-        "cpu_baseline_one_thread": cpu1,
-        "qps_at_095": {
-            "learned_bf16_measured": best_l and round(best_l["qps"], 1),
-            "learned_bf16_interp": interp_l and round(interp_l, 1),
-            "fp32_fixed_measured": best_f and round(best_f["qps"], 1),
-            "fp32_fixed_interp": interp_f and round(interp_f, 1),
-            "fp32_fixed_L": best_f and best_f["L"],
-            "bf16_rerank_fixed_measured": best_f16 and round(best_f16["qps"], 1),
-            "bf16_rerank_fixed_interp": interp_f16 and round(interp_f16, 1),
-            "bf16_rerank_fixed_L": best_f16 and best_f16["L"],
-            "fp8_rerank_fixed_measured": best_f8 and round(best_f8["qps"], 1),
-            "fp8_rerank_fixed_interp": interp_f8 and round(interp_f8, 1),
-            "fp8_rerank_fixed_L": best_f8 and best_f8["L"],
-        },
-        "kernel_ms": round(kern_ms, 4),
-        "host_filters_qps": round(e2e_qps, 1),
-        "alg_bytes_per_query": round(alg_bytes / nq, 1),
-        "mean_expansions": round(float(st[:, 0].mean()), 2),
-        "mean_distance_computations": round(float(st[:, 1].mean()), 2),
-        "build_seconds": round(build_s, 1),
-        "graph_build_seconds": build_times,
-        "sweeps": {"fixed": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
-                             for r in fixed],
-                   "bf16_rerank_fixed": [{k_: (round(v, 4) if isinstance(v, float) else v)
-                                          for k_, v in r.items()} for r in fixed16],
-                   "fp8_rerank_fixed": [{k_: (round(v, 4) if isinstance(v, float) else v)
-                                         for k_, v in r.items()} for r in fixed8],
-                   "learned": [{k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in r.items()}
-                               for r in learned]},
-        "predictor": fit_rep and fit_rep.__dict__,
-    }
-    print(json.dumps(out), flush=True)
+
+def _stats_params(sp, stats):
+    from paper_2602_10258_amd import jag
+    return jag.SearchParams(**{**sp.__dict__, "stats": stats})
 
 
 if __name__ == "__main__":
