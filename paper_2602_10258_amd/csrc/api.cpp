@@ -1,7 +1,11 @@
 // Host side of the C ABI declared in include/jag.h: argument checking,
 // index assembly, filter encoding with selectivity estimates, persistence.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -167,7 +171,24 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
                                const int32_t *pool, int64_t pool_len, FilterRecord *out,
                                unsigned char *tab_base, const int64_t *tpos)
 {
+    // range estimates read the rank index at two places per filter: the
+    // lines a few filters ahead are requested early, bucket bounds first
+    constexpr int64_t kAhead = 8;
+    auto bucket = [&](int64_t v) -> int64_t {
+        return v <= ix.scal_min || v > ix.scal_max ? -1 : (v - ix.scal_min) >> ix.scal_shift;
+    };
+    auto ahead = [&](int64_t qa, bool rows) {
+        if (qa >= q1 || F[qa].type != F_RANGE || !ix.has_scalar) return;
+        for (int64_t v : {(int64_t)F[qa].lo, (int64_t)F[qa].hi + 1}) {
+            const int64_t b = bucket(v);
+            if (b < 0) continue;
+            if (rows) __builtin_prefetch(ix.scalar_sorted.data() + ix.scal_cum[(size_t)b]);
+            else __builtin_prefetch(ix.scal_cum.data() + b);
+        }
+    };
     for (int64_t q = q0; q < q1; q++) {
+        ahead(q + 2 * kAhead, false);
+        ahead(q + kAhead, true);
         const jag_filter &f = F[q];
         FilterRecord r;
         std::memset(&r, 0, sizeof(r));
@@ -386,30 +407,106 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
     return JAG_OK;
 }
 
+// Host threads that encode the chunks of large batches.  Started on first
+// use and kept (one call's chunks at a time; a call that finds the pool busy
+// encodes its chunks itself), so a batch does not pay for starting threads.
+class EncodePool {
+  public:
+    static EncodePool &get()
+    {
+        static EncodePool p;
+        return p;
+    }
+    // fn(c) for every chunk c in [0, n); the caller takes chunks too
+    void run(int n, const std::function<void(int)> &fn)
+    {
+        std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
+        if (!busy.owns_lock() || workers_.empty()) {
+            for (int c = 0; c < n; c++) fn(c);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            fn_ = &fn;
+            n_ = n;
+            next_.store(0);
+            left_ = n;
+            gen_++;
+        }
+        cv_.notify_all();
+        drain();
+        std::unique_lock<std::mutex> lk(mu_);
+        done_.wait(lk, [&] { return left_ == 0; });
+        fn_ = nullptr;
+    }
+    ~EncodePool()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+    }
+
+  private:
+    EncodePool()
+    {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        for (unsigned t = 1; t < std::min(hw, 8u); t++) workers_.emplace_back([this] { loop(); });
+    }
+    void drain()
+    {
+        for (;;) {
+            const int c = next_.fetch_add(1);
+            if (c >= n_) return;
+            (*fn_)(c);
+            std::lock_guard<std::mutex> g(mu_);
+            if (--left_ == 0) done_.notify_all();
+        }
+    }
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || (gen_ != seen && fn_); });
+                if (stop_) return;
+                seen = gen_;
+            }
+            drain();
+        }
+    }
+    std::mutex run_mu_, mu_;
+    std::condition_variable cv_, done_;
+    std::vector<std::thread> workers_;
+    const std::function<void(int)> *fn_ = nullptr;
+    int n_ = 0, left_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
 static jag_status run_encode(const Index &ix, const jag_filter *F, int64_t nq, const int32_t *pool,
                              int64_t pool_len, FilterRecord *out, unsigned char *tab_base,
                              const int64_t *tpos)
 {
-    // large batches are encoded by several host threads
-    constexpr int64_t kPerThread = 2048;
-    const int nth = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()),
-                                           std::min<int64_t>(16, nq / kPerThread));
-    if (nth <= 1) return encode_range(ix, F, 0, nq, pool, pool_len, out, tab_base, tpos);
-    std::vector<jag_status> st(nth, JAG_OK);
-    std::vector<std::string> msg(nth);
-    std::vector<std::thread> th;
-    const int64_t chunk = (nq + nth - 1) / nth;
-    for (int t = 0; t < nth; t++)
-        th.emplace_back([&, t]() {
-            st[t] = encode_range(ix, F, t * chunk, std::min(nq, (t + 1) * chunk), pool, pool_len, out,
-                                 tab_base, tpos);
-            if (st[t] != JAG_OK) msg[t] = g_err;  // the worker's own thread-local message
-        });
-    for (auto &x : th) x.join();
-    for (int t = 0; t < nth; t++)
-        if (st[t] != JAG_OK) {  // the first bad query in batch order
-            set_error("%s", msg[t].c_str());
-            return st[t];
+    // large batches are encoded in chunks by the pool's host threads
+    constexpr int64_t kChunk = 1024;
+    const int nch = (int)((nq + kChunk - 1) / kChunk);
+    if (nch <= 1) return encode_range(ix, F, 0, nq, pool, pool_len, out, tab_base, tpos);
+    std::vector<jag_status> st(nch, JAG_OK);
+    std::vector<std::string> msg(nch);
+    EncodePool::get().run(nch, [&](int c) {
+        st[c] = encode_range(ix, F, c * kChunk, std::min(nq, (c + 1) * kChunk), pool, pool_len, out, tab_base,
+                             tpos);
+        if (st[c] != JAG_OK) msg[c] = g_err;  // the worker's own thread-local message
+    });
+    for (int c = 0; c < nch; c++)
+        if (st[c] != JAG_OK) {  // the first bad query in batch order
+            set_error("%s", msg[c].c_str());
+            return st[c];
         }
     return JAG_OK;
 }

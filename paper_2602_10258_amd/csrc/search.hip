@@ -94,6 +94,13 @@ __device__ __forceinline__ int lanes_below(uint64_t mask)
 // literals to flip in the cheapest satisfiable clause; general Boolean
 // function (truth table) -> its precomputed distance table at the item's
 // assignment of the function's variables.
+// Which attributes an index's items carry; kernels are built per kind so
+// that an index with scalars only (range filters) or labels only carries no
+// code or registers for the other kind.  On an index of one kind the
+// encoder accepts only that kind's filters; a record of the other kind
+// would get dist_F = "never satisfied".
+enum AttrKind { AK_ANY = 0, AK_SCALAR = 1, AK_LABELS = 2 };
+
 // The attribute words of one item as the filter needs them: the scalar for
 // a range filter, else the label row (two uint16 labels per word, 0xFFFF
 // padded).
@@ -127,10 +134,11 @@ __device__ __forceinline__ void load_label_words(uint32_t *w, const unsigned cha
 }
 
 // from the per-item attribute arrays
+template <int AK>
 __device__ __forceinline__ void load_item_attr(ItemAttr &at, const FilterRecord &f, int32_t u,
                                                const SearchArgs &a)
 {
-    if (f.type == F_RANGE) {
+    if (AK == AK_SCALAR || (AK == AK_ANY && f.type == F_RANGE)) {
         at.scalar = a.scalar[u];
         return;
     }
@@ -139,10 +147,11 @@ __device__ __forceinline__ void load_item_attr(ItemAttr &at, const FilterRecord 
 
 // from the adjacency row of the vertex being expanded: the row carries, after
 // the R neighbour ids, each neighbour's scalar and label words (slot j)
+template <int AK>
 __device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &f, const int32_t *row,
                                               int j, const SearchArgs &a)
 {
-    if (f.type == F_RANGE) {
+    if (AK == AK_SCALAR || (AK == AK_ANY && f.type == F_RANGE)) {
         at.scalar = row[a.scal_word_off + j];
         return;
     }
@@ -150,15 +159,17 @@ __device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &
                      a.W >> 1);
 }
 
+template <int AK>
 __device__ __forceinline__ uint32_t dist_f(const FilterRecord &f, const uint8_t *tab, const ItemAttr &at,
                                            const SearchArgs &a)
 {
-    if (f.type == F_RANGE) {
+    if (AK != AK_LABELS && f.type == F_RANGE) {
         int64_t v = at.scalar;
         if (v < f.a) return (uint32_t)((int64_t)f.a - v);
         if (v > f.b) return (uint32_t)(v - (int64_t)f.b);
         return 0u;
     }
+    if (AK == AK_SCALAR || (AK == AK_LABELS && f.type == F_RANGE)) return kUnsat;
     const uint32_t *w = at.w;
     int nw = a.W >> 1;
     // static loop bounds keep the (uniform) record in scalar registers
@@ -362,21 +373,21 @@ __host__ __device__ constexpr size_t lds_bytes(int Lcap, int H)
            64 * 4;
 }
 
-// Insert id u into the lossy hash; true if u was not found (newly seen).
+// Insert id u into the lossy seen-table; true if u was not found (newly
+// seen).  The table is a set of 4-slot buckets read with one 16-byte LDS
+// load: u is looked for in its bucket, then stored in the first empty slot,
+// or over a slot chosen by its hash when the bucket is full.  Lanes that
+// insert into one bucket at once may overwrite each other's ids; either way
+// the table only forgets ids, it never reports one it was not given.
 __device__ __forceinline__ bool hash_insert(int32_t *hash, int mask, int32_t u)
 {
     uint32_t h = (uint32_t)u * 0x9E3779B1u;
     h ^= h >> 15;
-    for (int t = 0; t < 4; t++) {
-        int s = (int)((h + t) & (uint32_t)mask);
-        int32_t v = hash[s];
-        if (v == u) return false;
-        if (v == -1) {
-            hash[s] = u;
-            return true;
-        }
-    }
-    hash[h & (uint32_t)mask] = u;
+    const int b = (int)(h & (uint32_t)mask) & ~3;
+    const int4 v = *reinterpret_cast<const int4 *>(hash + b);
+    if (v.x == u || v.y == u || v.z == u || v.w == u) return false;
+    const int slot = v.x == -1 ? 0 : v.y == -1 ? 1 : v.z == -1 ? 2 : v.w == -1 ? 3 : (int)((h >> 20) & 3u);
+    hash[b + slot] = u;
     return true;
 }
 
@@ -423,10 +434,8 @@ __device__ __forceinline__ int merge_small(const Lds &s, int cnt, int ls, bool h
         const uint64_t dk = ((uint64_t)dkh << 32) | dkl;
         const int pd = __popcll(ballot64(inl && key_lt(lk, li, dk, di)));
         const bool isdup = ballot64(inl && lk == dk && li == di) != 0;
-        if (lane == d) {
-            mypos = pd;
-            dup = isdup;
-        }
+        mypos = lane == d ? pd : mypos;
+        dup = lane == d ? isdup : dup;
         if (!isdup) {
             nkeep++;
             sh += (inl && pd <= lane) ? 1 : 0;
@@ -580,8 +589,9 @@ __device__ float predict(const Lds &s, const uint16_t *P)
     return t + bf16f(b3[0]);
 }
 
-// WPE: occupancy target (waves per SIMD) the register allocator works to.
-template <int STORE, int G, int CH, int WPE, int SL>
+// WPE: occupancy target (waves per SIMD) the register allocator works to;
+// SL: 64-neighbour slices per row (2 for R up to 128); AK: AttrKind.
+template <int STORE, int G, int CH, int WPE, int SL, int AK>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void search_kernel(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -637,8 +647,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         if (lane == 0) {
             s.cid[0] = a.entry;
             ItemAttr at;
-            load_item_attr(at, f, a.entry, a);
-            s.cdf[0] = dist_f(f, tab, at, a);
+            load_item_attr<AK>(at, f, a.entry, a);
+            s.cdf[0] = dist_f<AK>(f, tab, at, a);
         }
         __syncthreads();
         eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, 1, qr);
@@ -673,10 +683,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
             ItemAttr at;
             if (h + lane < a.R) {
                 u = row[h + lane];
-                load_row_attr(at, f, row, h + lane, a);
+                load_row_attr<AK>(at, f, row, h + lane, a);
             }
             bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
-            uint32_t df = fresh ? dist_f(f, tab, at, a) : 0u;
+            uint32_t df = fresh ? dist_f<AK>(f, tab, at, a) : 0u;
             nattr += __popcll(ballot64(fresh));
             if (cnt == ls) fresh = fresh && df <= (uint32_t)(s.key[cnt - 1] >> 32);
             uint64_t bm = ballot64(fresh);
@@ -732,9 +742,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
                     float c = ceilf(z);
                     idx = c < 0.f ? 0 : (c > (float)(a.nladder - 1) ? a.nladder - 1 : (int)c);
                 }
-#pragma unroll
-                for (int i = 0; i < JAG_LADDER_MAX; i++)
-                    if (i == idx) lhat = a.ladder[i];
+                lhat = a.ladder[idx];  // read from the kernel arguments when needed
                 float capf = ceilf(a.rho * (float)lhat);
                 int cap = capf >= 2147483647.0f ? INT_MAX : (int)capf;
                 cap = cap < 4 ? 4 : cap;
@@ -846,8 +854,8 @@ __global__ __launch_bounds__(64) void exact_kernel(SearchArgs a, int64_t n)
         uint32_t df = 1u;
         if (ok) {
             ItemAttr at;
-            load_item_attr(at, f, (int32_t)i, a);
-            df = dist_f(f, tab, at, a);
+            load_item_attr<AK_ANY>(at, f, (int32_t)i, a);
+            df = dist_f<AK_ANY>(f, tab, at, a);
         }
         ok = ok && df == 0;
         uint64_t bm = ballot64(ok);
@@ -1081,37 +1089,66 @@ jag_status dalloc(T **p, size_t bytes, int64_t &acct)
     return JAG_OK;
 }
 
-int pick_group(int stride) { return stride <= 512 ? 4 : 16; }
+// Lanes per vector row: 4 for rows of up to 384 bytes, 8 up to 512 bytes,
+// 16 beyond; rows are padded to a multiple of 16 * G bytes.  On the label-set
+// workload (FP32 rows of 512 bytes) 8 lanes of 4 chunks ran 10-17 % faster
+// than 4 lanes of 8 chunks, which spill registers; on 384-byte rows 4 lanes
+// of 6 chunks stay 2 % ahead of 8 lanes of 3.
+int pick_group(int stride) { return stride <= 384 ? 4 : stride <= 512 ? 8 : 16; }
+
+int padded_stride(int stride)
+{
+    const int unit = 16 * pick_group(stride);
+    return (stride + unit - 1) / unit * unit;
+}
 
 using SearchFn = void (*)(SearchArgs);
 using ExactFn = void (*)(SearchArgs, int64_t);
 
-template <int STORE, int G, int WPE, int SL>
+// Chunks of 16 bytes per lane: 4 lanes take rows of up to 384 bytes (1..6
+// chunks), 8 lanes rows of 512 (4), 16 lanes wider rows padded to 256 bytes
+// (3..8).
+template <int STORE, int G, int WPE, int SL, int AK>
 SearchFn search_for_ch(int ch)
 {
-    switch (ch) {
-    case 1: return search_kernel<STORE, G, 1, WPE, SL>;
-    case 2: return search_kernel<STORE, G, 2, WPE, SL>;
-    case 3: return search_kernel<STORE, G, 3, WPE, SL>;
-    case 4: return search_kernel<STORE, G, 4, WPE, SL>;
-    case 5: return search_kernel<STORE, G, 5, WPE, SL>;
-    case 6: return search_kernel<STORE, G, 6, WPE, SL>;
-    case 7: return search_kernel<STORE, G, 7, WPE, SL>;
-    case 8: return search_kernel<STORE, G, 8, WPE, SL>;
+    if (G == 4 && ch >= 1 && ch <= 6) {
+        switch (ch) {
+        case 1: return search_kernel<STORE, G, 1, WPE, SL, AK>;
+        case 2: return search_kernel<STORE, G, 2, WPE, SL, AK>;
+        case 3: return search_kernel<STORE, G, 3, WPE, SL, AK>;
+        case 4: return search_kernel<STORE, G, 4, WPE, SL, AK>;
+        case 5: return search_kernel<STORE, G, 5, WPE, SL, AK>;
+        case 6: return search_kernel<STORE, G, 6, WPE, SL, AK>;
+        }
+    }
+    if (G == 8 && ch == 4) return search_kernel<STORE, G, 4, WPE, SL, AK>;
+    if (G == 16) {
+        switch (ch) {
+        case 3: return search_kernel<STORE, G, 3, WPE, SL, AK>;
+        case 4: return search_kernel<STORE, G, 4, WPE, SL, AK>;
+        case 5: return search_kernel<STORE, G, 5, WPE, SL, AK>;
+        case 6: return search_kernel<STORE, G, 6, WPE, SL, AK>;
+        case 7: return search_kernel<STORE, G, 7, WPE, SL, AK>;
+        case 8: return search_kernel<STORE, G, 8, WPE, SL, AK>;
+        }
     }
     return nullptr;
 }
 
-template <int WPE, int SL>
+template <int WPE, int SL, int AK>
 SearchFn pick_search_sl(int store, int G, int ch)
 {
     if (store == JAG_STORE_F32)
-        return G == 4 ? search_for_ch<JAG_STORE_F32, 4, WPE, SL>(ch) : search_for_ch<JAG_STORE_F32, 16, WPE, SL>(ch);
+        return G == 4   ? search_for_ch<JAG_STORE_F32, 4, WPE, SL, AK>(ch)
+               : G == 8 ? search_for_ch<JAG_STORE_F32, 8, WPE, SL, AK>(ch)
+                        : search_for_ch<JAG_STORE_F32, 16, WPE, SL, AK>(ch);
     if (store == JAG_STORE_BF16)
-        return G == 4 ? search_for_ch<JAG_STORE_BF16, 4, WPE, SL>(ch)
-                      : search_for_ch<JAG_STORE_BF16, 16, WPE, SL>(ch);
-    return G == 4 ? search_for_ch<JAG_STORE_FP8_E4M3, 4, WPE, SL>(ch)
-                  : search_for_ch<JAG_STORE_FP8_E4M3, 16, WPE, SL>(ch);
+        return G == 4   ? search_for_ch<JAG_STORE_BF16, 4, WPE, SL, AK>(ch)
+               : G == 8 ? search_for_ch<JAG_STORE_BF16, 8, WPE, SL, AK>(ch)
+                        : search_for_ch<JAG_STORE_BF16, 16, WPE, SL, AK>(ch);
+    return G == 4   ? search_for_ch<JAG_STORE_FP8_E4M3, 4, WPE, SL, AK>(ch)
+           : G == 8 ? search_for_ch<JAG_STORE_FP8_E4M3, 8, WPE, SL, AK>(ch)
+                    : search_for_ch<JAG_STORE_FP8_E4M3, 16, WPE, SL, AK>(ch);
 }
 
 // All modes use the build for 5 waves per SIMD (at most 96 VGPRs; the
@@ -1123,26 +1160,41 @@ SearchFn pick_search_sl(int store, int G, int ch)
 constexpr int kWavesPerSimd = 5;
 
 // Rows of more than 64 neighbours take the two-slice build (the one-slice
-// build has no slice loop, which keeps its register allocation).
-SearchFn pick_search(int store, int stride, int R)
+// build has no slice loop, which keeps its register allocation); rows of up
+// to 64 take the build for the index's attribute kind.
+SearchFn pick_search(int store, int stride, int R, int ak)
 {
     int G = pick_group(stride);
     int ch = stride / (16 * G);
-    return R <= 64 ? pick_search_sl<kWavesPerSimd, 1>(store, G, ch) : pick_search_sl<kWavesPerSimd, 2>(store, G, ch);
+    if (R > 64) return pick_search_sl<kWavesPerSimd, 2, AK_ANY>(store, G, ch);
+    if (ak == AK_SCALAR) return pick_search_sl<kWavesPerSimd, 1, AK_SCALAR>(store, G, ch);
+    if (ak == AK_LABELS) return pick_search_sl<kWavesPerSimd, 1, AK_LABELS>(store, G, ch);
+    return pick_search_sl<kWavesPerSimd, 1, AK_ANY>(store, G, ch);
 }
 
 template <int G>
 ExactFn exact_for_ch(int ch)
 {
-    switch (ch) {
-    case 1: return exact_kernel<G, 1>;
-    case 2: return exact_kernel<G, 2>;
-    case 3: return exact_kernel<G, 3>;
-    case 4: return exact_kernel<G, 4>;
-    case 5: return exact_kernel<G, 5>;
-    case 6: return exact_kernel<G, 6>;
-    case 7: return exact_kernel<G, 7>;
-    case 8: return exact_kernel<G, 8>;
+    if (G == 4 && ch >= 1 && ch <= 6) {
+        switch (ch) {
+        case 1: return exact_kernel<G, 1>;
+        case 2: return exact_kernel<G, 2>;
+        case 3: return exact_kernel<G, 3>;
+        case 4: return exact_kernel<G, 4>;
+        case 5: return exact_kernel<G, 5>;
+        case 6: return exact_kernel<G, 6>;
+        }
+    }
+    if (G == 8 && ch == 4) return exact_kernel<G, 4>;
+    if (G == 16) {
+        switch (ch) {
+        case 3: return exact_kernel<G, 3>;
+        case 4: return exact_kernel<G, 4>;
+        case 5: return exact_kernel<G, 5>;
+        case 6: return exact_kernel<G, 6>;
+        case 7: return exact_kernel<G, 7>;
+        case 8: return exact_kernel<G, 8>;
+        }
     }
     return nullptr;
 }
@@ -1238,7 +1290,7 @@ jag_status upload_index(Index &ix)
         return JAG_EDEVICE;
     }
     ix.vec_stride = store_row_bytes(ix.store, d);
-    if (pick_group(ix.vec_stride) == 16) ix.vec_stride = (ix.vec_stride + 255) / 256 * 256;
+    ix.vec_stride = padded_stride(ix.vec_stride);
     if ((st = dalloc(&ix.d_vec, (size_t)n * ix.vec_stride, ix.device_bytes)) != JAG_OK) {
         cleanup();
         return st;
@@ -1257,7 +1309,7 @@ jag_status upload_index(Index &ix)
             quant_fp8_kernel<<<(unsigned)n, 64>>>(dX, n, d, ix.d_vec, ix.vec_stride);
         }
         if (ix.keep_f32) {
-            ix.f32_stride = (4 * d + 63) / 64 * 64;
+            ix.f32_stride = padded_stride((4 * d + 63) / 64 * 64);
             if ((st = dalloc(&ix.d_f32, (size_t)n * ix.f32_stride, ix.device_bytes)) != JAG_OK) {
                 cleanup();
                 return st;
@@ -1430,7 +1482,9 @@ static jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void 
     int H = S.hash_log2 ? (1 << S.hash_log2) : kDefaultHash;
     a.Lcap = Lcap;
     a.Hmask = H - 1;
-    fn = pick_search(ix.store, ix.vec_stride, ix.R);
+    const int ak = ix.has_scalar && !ix.has_labels ? AK_SCALAR : !ix.has_scalar && ix.has_labels ? AK_LABELS
+                                                                                                  : AK_ANY;
+    fn = pick_search(ix.store, ix.vec_stride, ix.R, ak);
     if (!fn) {
         set_error("no kernel for row stride %d", ix.vec_stride);
         return JAG_EUNSUPPORTED;
@@ -1613,8 +1667,8 @@ jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *recor
     a.Hmask = 0;
     int G = pick_group(ix.f32_stride);
     int ch = ix.f32_stride / (16 * G);
-    ExactFn fn = G == 4 ? exact_for_ch<4>(ch) : exact_for_ch<16>(ch);
-    if (!fn || (G == 16 && ix.f32_stride % 256)) {
+    ExactFn fn = G == 4 ? exact_for_ch<4>(ch) : G == 8 ? exact_for_ch<8>(ch) : exact_for_ch<16>(ch);
+    if (!fn || ix.f32_stride % (16 * G)) {
         set_error("no exact kernel for FP32 row stride %d", ix.f32_stride);
         return JAG_EUNSUPPORTED;
     }

@@ -22,14 +22,19 @@ import numpy as np
 U = 2.0 ** -24
 
 
+def _layout(raw: int) -> tuple[int, int]:
+    """(row stride, lanes per row) of the GPU's layout for rows of `raw` bytes:
+    64-byte padding, then 4 lanes up to 384 bytes, 8 up to 512, 16 beyond, and
+    padding to a multiple of 16 bytes per lane."""
+    stride = (raw + 63) // 64 * 64
+    G = 4 if stride <= 384 else 8 if stride <= 512 else 16
+    return (stride + 16 * G - 1) // (16 * G) * (16 * G), G
+
+
 def row_terms(store: int, d: int) -> tuple[int, int]:
     """(terms per lane, lanes per row) of the GPU distance for a store and dimension."""
     eb = {0: 4, 1: 2, 2: 1}[store]
-    raw = eb * d + (4 if store == 2 else 0)
-    stride = (raw + 63) // 64 * 64
-    G = 4 if stride <= 512 else 16
-    if G == 16:
-        stride = (stride + 255) // 256 * 256
+    stride, G = _layout(eb * d + (4 if store == 2 else 0))
     ch = stride // (16 * G)
     epc = 16 // eb
     return ch * epc, G
@@ -41,13 +46,9 @@ def lane_order(store: int, d: int) -> list[int]:
     of the FP32 rows the rerank reads (four lanes over 64-byte-padded rows,
     or the store's own rows for an FP32 store)."""
     eb = {0: 4, 1: 2, 2: 1}[store]
-    raw = eb * d + (4 if store == 2 else 0)
-    stride = (raw + 63) // 64 * 64
-    G = 4 if stride <= 512 else 16
-    if G == 16:
-        stride = (stride + 255) // 256 * 256
+    stride, G = _layout(eb * d + (4 if store == 2 else 0))
     out = [G, 16 // eb, stride // (16 * G)]
-    f32_stride = stride if store == 0 else (4 * d + 63) // 64 * 64
+    f32_stride = stride if store == 0 else _layout(4 * d)[0]
     return out + [4, 4, f32_stride // 64]
 
 
