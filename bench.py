@@ -59,9 +59,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default=None,
                     help="run only this workload's legs (default: every leg of --legs)")
-    ap.add_argument("--legs", default="c2:range,c1:label,c3:subset,c3:boolean,c5:label",
+    ap.add_argument("--legs", default="c2:range,c1:label,c3:subset,c3:boolean,c5:label,c5:serve",
                     help="workload:filter-type legs; the first is the headline (timed steps, "
-                         "counters, full CPU baseline)")
+                         "counters, full CPU baseline); c5:serve is the serving leg (Poisson "
+                         "arrivals, batch and slot admission)")
+    ap.add_argument("--serve-rates", default="25000,100000,200000",
+                    help="offered rates of the serving leg (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="arrivals per rate and admission mode of the serving leg (seconds)")
+    ap.add_argument("--serve-queries", type=int, default=4000,
+                    help="distinct mixed queries of the serving leg (exact answers from the oracle)")
     ap.add_argument("--no-c4", action="store_true", help="skip the predictor evaluation at 200k traces")
     ap.add_argument("--c4-train", type=int, default=200000)
     ap.add_argument("--c4-heldout", type=int, default=10000)
@@ -88,6 +95,8 @@ def parse():
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
     ap.add_argument("--serve", action="store_true", help="serving benchmark (Poisson arrivals)")
     ap.add_argument("--rates", default="5000,20000,50000,100000,200000")
+    ap.add_argument("--admission", default="slots", choices=["slots", "batches"],
+                    help="--serve: how the server admits requests (resident waves, or batches per stream)")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="profile mode: also run device copies of this many bytes")
     ap.add_argument("--min-valid", type=int, default=None,
@@ -333,7 +342,10 @@ def serve_main(args):
     for qps in rates:
         m = min(w.nq, max(2000, int(qps * 1.0)))
         arr = poisson_arrivals(np.random.default_rng(int(qps)), m, qps)
-        s = jag.jag_server_start(ix, k, sp, max_batch=4096, n_streams=4, max_wait_us=100)
+        if args.admission == "slots":
+            s = jag.jag_server_start(ix, k, sp, slot_admission=True)
+        else:
+            s = jag.jag_server_start(ix, k, sp, max_batch=4096, n_streams=4, max_wait_us=100)
         t0 = time.perf_counter()
         tick = np.empty(m, dtype=np.uint64)
         i = 0
@@ -352,7 +364,7 @@ def serve_main(args):
             got[q] = jag.jag_server_poll(s, int(tick[q]))[0]
         jag.jag_server_stop(s)
         r = recall_of(got)
-        row = {"offered_qps": qps, "requests": m, "achieved_qps": round(st["qps"], 1),
+        row = {"admission": args.admission, "offered_qps": qps, "requests": m, "achieved_qps": round(st["qps"], 1),
                "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
                "mean_batch": round(st["mean_batch"], 1), "max_inflight": st["max_inflight_seen"],
                "resident_capacity": st["resident_capacity"], "recall_at_10": round(r, 4)}
@@ -364,6 +376,110 @@ def serve_main(args):
                       "delta": delta, "rho": rho},
            "rates": per_rate}
     print(json.dumps(out), flush=True)
+
+
+def poisson_run(jag, s, Q, F, pool, arrivals, k):
+    """Submit request i at arrivals[i] (seconds from now; query i mod len(Q)),
+    wait for all, return (ids[m, k], server stats)."""
+    m, nq = len(arrivals), len(Q)
+    qi = np.arange(m) % nq
+    t0 = time.perf_counter()
+    tick = np.empty(m, dtype=np.uint64)
+    i = 0
+    while i < m:
+        now = time.perf_counter() - t0
+        j = int(np.searchsorted(arrivals, now, side="right"))
+        if j > i:
+            tick[i:j] = jag.jag_server_submit(s, Q[qi[i:j]], F[qi[i:j]], pool)
+            i = j
+        else:
+            time.sleep(max(0.0, min(1e-4, arrivals[i] - now)))
+    jag.jag_server_drain(s)
+    st = jag.jag_server_stats_get(s)
+    got = np.empty((m, k), dtype=np.int32)
+    for q in range(m):
+        got[q] = jag.jag_server_poll(s, int(tick[q]))[0]
+    return got, st
+
+
+def serve_leg(args, cfg):
+    """Serving on the shard workload: Poisson arrivals of mixed Label, Range,
+    Subset and Boolean queries at a few offered rates, the learned beam (one
+    pass) over the FP8 store with the FP32 rerank at recall 0.95, through the
+    server with batch admission and with slot admission (resident waves that
+    take one request at a time).  p50/p99 latency from submit to the host
+    seeing the answer, per rate and admission mode."""
+    from oracle import oracle as O
+    from paper_2602_10258_amd import jag
+    from paper_2602_10258_amd import predictor as pred
+    from workloads.gen import extra_queries, poisson_arrivals
+    torch = cfg.torch
+    w, k, dev = cfg.w, cfg.w.k, cfg.dev
+    t0 = time.time()
+    ix = cfg.ix8()
+    Q, F, pool = extra_queries(w, args.serve_queries, qseed=7000)
+    gi, _, nv = O.bruteforce(w.X, cfg.A, Q, F, pool, k, nthreads=cfg.nthr)
+    keep = nv >= k
+    Q, F, gi, nv = np.ascontiguousarray(Q[keep]), np.ascontiguousarray(F[keep]), gi[keep], nv[keep]
+    nq = len(Q)
+    log(f"[serve] {nq} mixed queries with >= k valid items, exact answers in {time.time() - t0:.1f}s")
+
+    def recall_of(ids_np, qi):
+        return float(np.mean([len(set(gi[q, :k].tolist()) & set(ids_np[i].tolist())) / k
+                              for i, q in enumerate(qi)]))
+
+    rec = torch.from_numpy(jag.jag_encode_filters(ix, F, pool)).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    dd = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    cnt = torch.empty((nq,), dtype=torch.int32, device=dev)
+    allq = np.arange(nq)
+
+    def batch_recall(sp):
+        jag.jag_search_encoded(ix, Qd, rec, k, sp, ids, dd, cnt)
+        torch.cuda.synchronize()
+        return recall_of(ids.cpu().numpy(), allq)
+
+    L95 = next((L for L in LADDER_FIXED if batch_recall(jag.SearchParams(L=L, rerank_mult=4)) >= 0.95), None)
+    Qt, Ft, pt = extra_queries(w, args.ntrain, qseed=1000)
+    delta, lad, rho = None, None, None
+    for top in ladder_tops(L95, args.ladder_top):
+        lad = learned_ladder(L95, top)
+        _, rho, rep = pred.fit(ix, Qt, Ft, pt, k=k, rerank_mult=4, ladder=lad)
+        for dl in [0.0, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0]:
+            r = batch_recall(jag.SearchParams(L=k, learned=1, delta=dl, rerank_mult=4, single_pass=1))
+            if r >= 0.95:
+                delta = dl
+                break
+        if delta is not None:
+            break
+    delta = 6.0 if delta is None else delta
+    sp = jag.SearchParams(L=k, learned=1, delta=delta, rerank_mult=4)
+    log(f"[serve] fixed beam at 0.95: {L95}; ladder {lad.tolist()}, delta {delta}, rho {rho:.2f}")
+    rows = []
+    for mode in ("batches", "slots"):
+        for qps in [float(x) for x in args.serve_rates.split(",")]:
+            m = max(3000, int(qps * args.serve_seconds))
+            arr = poisson_arrivals(np.random.default_rng(int(qps)), m, qps)
+            if mode == "slots":
+                s = jag.jag_server_start(ix, k, sp, slot_admission=True)
+            else:
+                s = jag.jag_server_start(ix, k, sp, max_batch=4096, n_streams=4, max_wait_us=100)
+            try:
+                got, st = poisson_run(jag, s, Q, F, pool, arr, k)
+            finally:
+                jag.jag_server_stop(s)
+            row = {"admission": mode, "offered_qps": qps, "requests": m, "achieved_qps": round(st["qps"], 1),
+                   "p50_ms": round(st["p50_us"] / 1e3, 3), "p99_ms": round(st["p99_us"] / 1e3, 3),
+                   "max_ms": round(st["max_us"] / 1e3, 3), "launches": st["batches"],
+                   "max_inflight": st["max_inflight_seen"], "resident_capacity": st["resident_capacity"],
+                   "recall_at_10": round(recall_of(got, np.arange(m) % nq), 4)}
+            log(f"[serve] {row}")
+            rows.append(row)
+    return {"workload": f"{w.name} shard: {w.n} x {w.d}, FP8 E4M3 + row scale + FP32 rerank, R={w.R}, "
+                        f"equal mix of label/range/subset/Boolean filters, Poisson arrivals",
+            "queries": nq, "fixed_L_at_095": L95, "ladder": lad.tolist(), "delta": delta, "rho": round(rho, 3),
+            "rates": rows, "seconds": round(time.time() - t0, 1)}
 
 
 FILTER_CODES = {"label": 0, "range": 1, "subset": 2, "boolean": 3, "table": 4}
@@ -892,23 +1008,34 @@ def main():
                                                                "bool15": ["table"]}[args.config]]
     timer = Timer()
     configs, results = {}, {}
-    headline = {}
+    headline, serving = {}, None
     t_all = time.time()
+    search_legs = [l for l in legs if l[1] != "serve"]
     for i, (cname, tname) in enumerate(legs):
         if cname not in configs:
             # one workload's graph and indexes at a time on the device
             configs.clear()
-            configs[cname] = Config(args, cname, dev, [FILTER_CODES[t] for c, t in legs if c == cname])
-        out, op = run_leg(args, configs[cname], FILTER_CODES[tname], timer, headline=i == 0)
+            types = [FILTER_CODES[t] for c, t in legs if c == cname and t != "serve"]
+            configs[cname] = Config(args, cname, dev, types or None)
+        if tname == "serve":
+            serving = serve_leg(args, configs[cname])
+            log(f"leg {tname}:{cname} done at {time.time() - t_all:.0f}s")
+            continue
+        first = (cname, tname) == search_legs[0]
+        out, op = run_leg(args, configs[cname], FILTER_CODES[tname], timer, headline=first)
         results[f"{tname}:{cname}"] = out
-        if i == 0:
+        if first:
             headline = timed_steps(args, configs[cname], out, op)
         log(f"leg {tname}:{cname} done at {time.time() - t_all:.0f}s")
     configs.clear()
     c4 = None
     if not args.no_c4 and not args.config:
         c4 = predictor_eval(args, dev, timer)
-    hout = results[f"{legs[0][1]}:{legs[0][0]}"]
+    if not search_legs:
+        print(json.dumps({"metric": "serving latency (p50/p99) and QPS by admission mode", "serving": serving,
+                          "seconds": round(time.time() - t_all, 1)}, default=float), flush=True)
+        return
+    hout = results[f"{search_legs[0][1]}:{search_legs[0][0]}"]
     op = headline.get("op")
     learned_wins = {k_: (v.get("learned_over_bf16_fixed") or 0) > 1.0 for k_, v in results.items()}
     summary = {k_: {"fp32_fixed": v["qps_at_095"]["fp32_fixed"], "bf16_rerank_fixed": v["qps_at_095"]["bf16_rerank_fixed"],
@@ -923,7 +1050,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16" if op and op["store"] == 1 else "fp8" if op and op["store"] == 2 else "f32",
         "data": "synthetic",
-        "config": {"workload": hout["workload"], "filter_type": legs[0][1], "global_batch": hout["queries"],
+        "config": {"workload": hout["workload"], "filter_type": search_legs[0][1], "global_batch": hout["queries"],
                    "mode": op and op["mode"], "recall_at_10": headline.get("recall"),
                    "storage": op and STORE_NAMES[op["store"]], "accumulate": "fp32"},
         "roofline": hout.get("roofline"),
@@ -936,6 +1063,7 @@ def main():
         "learned_beats_bf16_fixed": learned_wins,
         "legs": results,
         "predictor_c4": c4,
+        "serving": serving,
         "seconds": round(time.time() - t_all, 1),
     }
     print(json.dumps(out, default=float), flush=True)

@@ -398,14 +398,30 @@ jag_status jag_predictor_grad(const float *features, const float *targets, int64
 /* ---- serving (not in the paper) ------------------------------------------ */
 
 /*
- * A server owns a scheduler thread that batches single queries as they
- * arrive and keeps several batches on the GPU at once (one HIP stream
- * each).  A request is admitted to the GPU when a stream is free and the
- * number of requests on the GPU stays within max_inflight, which defaults
- * to the number of query wavefronts the device can hold resident at once
- * (from the kernel's LDS and register needs).  Results are identical to a
- * jag_search_encoded call on the same query: queries share no state.
- * Per-request latency is measured from submit to the host seeing the result.
+ * A server owns a scheduler thread and admits single queries to the GPU in
+ * one of two ways (slot_admission):
+ *
+ *  0  batches: the thread gathers requests into batches and keeps several on
+ *     the GPU at once (one HIP stream each).  A batch is admitted when a
+ *     stream is free and the number of requests on the GPU stays within
+ *     max_inflight, which defaults to the number of query wavefronts the
+ *     device can hold resident at once (from the kernel's LDS and register
+ *     needs).
+ *  1  slots: one launch keeps up to max_inflight query wavefronts resident
+ *     (default: as many as the device holds, each with its own LDS), and
+ *     each wave takes the next request the moment its previous search ends.
+ *     Requests are published through a ring of pinned host memory that the
+ *     waves poll; answers are written straight back into pinned host memory.
+ *     The launch ends by itself after 10 ms without a new request and is
+ *     started again when requests arrive.  While it runs it holds the CUs it
+ *     occupies: other work on the device waits for free CUs.  learned must be
+ *     0 or 1 (1 runs the learned search in one pass); max_batch, n_streams
+ *     and max_wait_us are not used.
+ *
+ * Results are identical to a jag_search_encoded call on the same query with
+ * the same search parameters (learned one-pass for slot admission): queries
+ * share no state.  Per-request latency is measured from submit to the host
+ * seeing the result.
  */
 typedef struct jag_server jag_server;
 
@@ -418,12 +434,18 @@ typedef struct {
     int32_t max_wait_us;      /* a partial batch waits at most this long for company */
     int64_t max_inflight;     /* 0 = resident capacity of the device for this search */
     int64_t queue_capacity;   /* pending requests beyond this are refused (JAG_EBUSY) */
-    int64_t hbm_budget_bytes; /* 0 = no limit; else the server's device buffers (per stream:
-                                 a batch's queries, records and results, plus the saved
-                                 states of a two-pass learned search) must fit */
+    int64_t hbm_budget_bytes; /* 0 = no limit; else the server's device buffers (batches: per
+                                 stream a batch's queries, records and results, plus the saved
+                                 states of a two-pass learned search; slots: per wave a copy of
+                                 its query and a 32 KiB table copy) must fit */
+    int32_t slot_admission;   /* 0 = batches per stream, 1 = resident waves (see above) */
+    int32_t reserved;         /* must be 0 */
 } jag_server_params;
 
 typedef struct {
+    /* batches: launches of the search (slot admission: of the resident waves);
+     * max_inflight_seen: most requests published to the GPU and not yet
+     * returned at once (slot admission: including those waiting for a wave) */
     int64_t submitted, completed, batches, max_inflight_seen, resident_capacity;
     double p50_us, p99_us, mean_us, max_us; /* latency of completed requests */
     double qps;                             /* completed / (last completion - first submit) */

@@ -172,6 +172,49 @@ jag_status search_scratch_bytes(Index &ix, int32_t k, const jag_search_params &S
                                 int64_t *bytes);
 jag_status launch_exact(Index &ix, const float *Q, int64_t nq, const void *records, int32_t k,
                         int32_t *ids, float *dists, int32_t *count, void *stream);
+
+// Resident serving waves (serve_kernels.hip).  Requests sit in a ring of C
+// slots (C a power of two) in fine-grained pinned host memory; request h
+// uses slot h & (C - 1).  A slot holds the filter record (its table_off, for
+// a TABLE filter, is the table's byte offset in `tab`), at byte 128 the
+// sequence word h + 1, and from byte kServeSlotHeader the query vector.
+// The host writes a slot, then publishes it by raising ctl[0] (requests
+// published).  Waves claim published requests one at a time, search, write
+// the answer to the slot's result rows and then set done[slot] = h + 1.
+constexpr int kServeSlotHeader = 144;
+constexpr int kServeTableBytes = 1 << kMaxTableVars;  // per-wave table copy
+struct ServeRing {
+    const unsigned char *req;  // host: C slots of req_stride bytes
+    const unsigned char *tab;  // host: distance tables of TABLE requests (16-byte aligned)
+    int32_t *ids;              // host [C][k]
+    float *dists;              // host [C][k]
+    int32_t *count;            // host [C] (-1: the slot's sequence word was wrong)
+    uint64_t *done;            // host [C]: h + 1 once request h's answer is in place
+    const uint64_t *ctl;       // host: [0] requests published, [1] stop asked
+    // device: [kServeTicketWord] tickets handed out (request numbers),
+    // [kServeAvailWord] requests known to be published, top bit = closing,
+    // [kServeRaisedWord] wall-clock time of the last rise of that count
+    uint64_t *dctl;
+    unsigned char *wave_mem;   // device: per wave, a copy of its query, then of its table
+    int64_t wave_bytes;
+    int64_t poll_ticks;        // wall-clock ticks between polls of ctl
+    int64_t idle_ticks;        // the launch ends after this long without a new request
+    uint32_t cmask;            // C - 1
+    int32_t req_stride;
+};
+// The two device counters sit 256 bytes apart (separate cache lines).
+constexpr int kServeTicketWord = 0;
+constexpr int kServeAvailWord = 32;
+constexpr int kServeRaisedWord = 48;
+constexpr int kServeCtlWords = 64;
+// Bytes of wave_mem per wave for vectors of d elements.
+inline int64_t serve_wave_bytes(int32_t d) { return ((int64_t)4 * d + 255) / 256 * 256 + kServeTableBytes; }
+// Resident waves of the serving kernel the device holds at once.
+jag_status serve_capacity(Index &ix, int32_t k, const jag_search_params &S, int64_t *resident);
+// Launch `waves` serving waves on `stream`; they run until a stop is asked
+// or no request is claimed for idle_ticks.
+jag_status launch_serve(Index &ix, int32_t k, const jag_search_params &S, const ServeRing &r,
+                        int64_t waves, void *stream);
 jag_status upload_predictor(Index &ix);
 jag_status download_store(const Index &ix, void *rows_out, float *scales_out);
 jag_status train_predictor(const float *features, const float *targets, int64_t m,

@@ -1,17 +1,27 @@
-// Request server: continuous batching of single filtered queries.
+// Request server: single filtered queries admitted to the GPU as they come.
 //
-// Callers queue requests (jag_server_submit) from any thread.  A scheduler
-// thread keeps up to n_streams batches on the GPU, one HIP stream each:
-// whenever a stream is idle and requests are pending it gathers up to
-// max_batch of them -- without exceeding max_inflight requests on the GPU --
-// stages their vectors and filter records in pinned host memory, copies them
-// to the stream's device buffers, launches the search kernel and copies the
-// results back, all asynchronously on that stream.  Finished streams are
-// found with hipEventQuery and their requests completed.  New requests thus
-// join the device while earlier batches are still running, and batches on
-// different streams run concurrently.  Each query's beam lives in its own
-// wavefront's LDS for the whole search, so a result does not depend on the
-// batch it rode in.
+// Callers queue requests (jag_server_submit) from any thread; a scheduler
+// thread admits them in one of two ways.
+//
+// Batches: the thread keeps up to n_streams batches on the GPU, one HIP
+// stream each.  Whenever a stream is idle and requests are pending it
+// gathers up to max_batch of them -- without exceeding max_inflight requests
+// on the GPU --, stages their vectors and filter records in pinned host
+// memory, copies them to the stream's device buffers, launches the search
+// kernel and copies the results back, all asynchronously on that stream.
+// Finished streams are found with hipEventQuery and their requests
+// completed.
+//
+// Slots: one launch of resident waves (serve_kernels.hip) takes requests one
+// at a time.  The thread writes each request into the next free slot of a
+// ring in fine-grained pinned host memory and publishes it by raising a
+// counter there; a free wave claims it, searches, writes the answer into the
+// slot's result rows and marks the slot done.  The thread collects done
+// slots, frees them in order and starts the waves again whenever they have
+// ended (after an idle interval) with published requests left.
+//
+// Each query's beam lives in its own wavefront's LDS for the whole search,
+// so a result does not depend on the batch or the company it ran in.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,6 +78,42 @@ struct Slot {
     bool busy = false;
 };
 
+// Slot admission: the ring in fine-grained pinned host memory, the waves'
+// device memory, and the thread's bookkeeping per slot.
+struct Ring {
+    int64_t C = 0;
+    int64_t req_stride = 0;
+    unsigned char *h_req = nullptr;
+    unsigned char *h_tab = nullptr;
+    int64_t tab_cap = 0;
+    int32_t *h_ids = nullptr, *h_cnt = nullptr;
+    float *h_d = nullptr;
+    uint64_t *h_done = nullptr, *h_ctl = nullptr;
+    uint64_t *d_ctl = nullptr;
+    unsigned char *d_wave = nullptr;
+    jag::ServeRing view{};  // what the waves see (device addresses)
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    int64_t waves = 0;
+    bool running = false;
+    int64_t launches = 0;
+    // per slot: the request it holds, whether its answer was collected, and
+    // the table area's write position after its table
+    std::vector<uint64_t> ticket;
+    std::vector<clk::time_point> t_submit;
+    std::vector<uint8_t> collected;
+    std::vector<int64_t> tab_end;
+    int64_t published = 0;   // requests written to the ring
+    int64_t freed = 0;       // requests whose slots are free again (a prefix)
+    int64_t finished = 0;    // requests collected
+    int64_t tab_head = 0, tab_tail = 0;  // table area: next write, oldest live byte
+};
+
+constexpr int64_t kRingTableBytes = 8ll << 20;
+constexpr int64_t kServePollUs = 2;
+constexpr int64_t kServeIdleUs = 10000;
+constexpr int kServeStallS = 10;
+
 }  // namespace
 
 struct jag_server {
@@ -75,6 +121,8 @@ struct jag_server {
     jag_server_params P{};
     int64_t max_inflight = 0, resident = 0;
     std::vector<Slot> slots;
+    bool slot_mode = false;
+    Ring ring;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request> pending;
@@ -304,6 +352,291 @@ void worker_loop(jag_server *S)
     }
 }
 
+// ---------------------------------------------------------------- slots
+void free_ring(Ring &R)
+{
+    if (R.stream) (void)hipStreamSynchronize(R.stream);
+    if (R.stream) (void)hipStreamDestroy(R.stream);
+    if (R.event) (void)hipEventDestroy(R.event);
+    for (void *p : {(void *)R.h_req, (void *)R.h_tab, (void *)R.h_ids, (void *)R.h_cnt, (void *)R.h_d,
+                    (void *)R.h_done, (void *)R.h_ctl})
+        if (p) (void)hipHostFree(p);
+    for (void *p : {(void *)R.d_ctl, (void *)R.d_wave})
+        if (p) (void)hipFree(p);
+    R = Ring();
+}
+
+// Fine-grained pinned host memory, zeroed, and its device address.
+template <class T>
+bool host_coherent(T **h, int64_t bytes)
+{
+    if (!HIPOK(hipHostMalloc((void **)h, (size_t)bytes, hipHostMallocCoherent | hipHostMallocMapped))) {
+        *h = nullptr;
+        return false;
+    }
+    std::memset((void *)*h, 0, (size_t)bytes);
+    return true;
+}
+
+template <class T>
+bool device_address(T *h, T **d)
+{
+    void *p = nullptr;
+    if (!HIPOK(hipHostGetDevicePointer(&p, (void *)h, 0))) return false;
+    *d = static_cast<T *>(p);
+    return true;
+}
+
+int64_t ring_device_bytes(int64_t waves, int32_t d)
+{
+    return waves * jag::serve_wave_bytes(d) + jag::kServeCtlWords * (int64_t)sizeof(uint64_t);
+}
+
+jag_status alloc_ring(jag_server *S, int64_t waves)
+{
+    Ring &R = S->ring;
+    const int d = S->idx->ix.d, k = S->P.k;
+    int64_t C = 1024;
+    while (C < 2 * waves) C *= 2;
+    R.C = C;
+    R.req_stride = jag::kServeSlotHeader + ((int64_t)4 * d + 15) / 16 * 16;
+    R.tab_cap = kRingTableBytes;
+    R.waves = waves;
+    int rate_khz = 0;
+    bool ok = HIPOK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, S->idx->ix.device)) &&
+              rate_khz > 0 && host_coherent(&R.h_req, C * R.req_stride) &&
+              host_coherent(&R.h_tab, R.tab_cap) && host_coherent(&R.h_ids, C * k * 4) &&
+              host_coherent(&R.h_d, C * k * 4) && host_coherent(&R.h_cnt, C * 4) &&
+              host_coherent(&R.h_done, C * 8) && host_coherent(&R.h_ctl, 64) &&
+              HIPOK(hipMalloc((void **)&R.d_ctl, jag::kServeCtlWords * sizeof(uint64_t))) &&
+              HIPOK(hipMemset(R.d_ctl, 0, jag::kServeCtlWords * sizeof(uint64_t))) &&
+              HIPOK(hipMalloc((void **)&R.d_wave, (size_t)(waves * jag::serve_wave_bytes(d)))) &&
+              HIPOK(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking)) &&
+              HIPOK(hipEventCreateWithFlags(&R.event, hipEventDisableTiming));
+    jag::ServeRing &v = R.view;
+    ok = ok && device_address(R.h_req, const_cast<unsigned char **>(&v.req)) &&
+         device_address(R.h_tab, const_cast<unsigned char **>(&v.tab)) && device_address(R.h_ids, &v.ids) &&
+         device_address(R.h_d, &v.dists) && device_address(R.h_cnt, &v.count) &&
+         device_address(R.h_done, &v.done) && device_address(R.h_ctl, const_cast<uint64_t **>(&v.ctl));
+    if (!ok) {
+        free_ring(R);
+        jag::set_error("server ring allocation failed");
+        return JAG_ENOMEM;
+    }
+    const int64_t per_us = std::max<int64_t>(1, rate_khz / 1000);
+    v.dctl = R.d_ctl;
+    v.wave_mem = R.d_wave;
+    v.wave_bytes = jag::serve_wave_bytes(d);
+    v.poll_ticks = kServePollUs * per_us;
+    v.idle_ticks = kServeIdleUs * per_us;
+    v.cmask = (uint32_t)(C - 1);
+    v.req_stride = (int32_t)R.req_stride;
+    R.ticket.assign(C, 0);
+    R.t_submit.assign(C, clk::time_point{});
+    R.collected.assign(C, 1);
+    R.tab_end.assign(C, 0);
+    return JAG_OK;
+}
+
+// Write pending requests into free ring slots (lock held); returns how many.
+int64_t ring_publish(jag_server *S)
+{
+    Ring &R = S->ring;
+    const int d = S->idx->ix.d;
+    int64_t n = 0;
+    while (!S->pending.empty() && R.published - R.freed < R.C) {
+        Request &q = S->pending.front();
+        int64_t tpos = -1, tend = R.tab_head;
+        if (!q.table.empty()) {
+            const int64_t size = std::max<int64_t>(16, ((int64_t)q.table.size() + 15) / 16 * 16);
+            int64_t head = R.tab_head;
+            if (head % R.tab_cap + size > R.tab_cap) head += R.tab_cap - head % R.tab_cap;  // wrap
+            if (head + size - R.tab_tail > R.tab_cap) break;  // wait for tables to be freed
+            tpos = head % R.tab_cap;
+            std::memcpy(R.h_tab + tpos, q.table.data(), q.table.size());
+            tend = head + size;
+        }
+        const int64_t h = R.published;
+        const int64_t slot = h & (R.C - 1);
+        unsigned char *p = R.h_req + slot * R.req_stride;
+        jag::FilterRecord rec = q.rec;
+        if (tpos >= 0) rec.table_off = tpos;
+        std::memcpy(p, &rec, sizeof rec);
+        const uint64_t seq = (uint64_t)h + 1;
+        std::memcpy(p + 128, &seq, sizeof seq);
+        std::memcpy(p + jag::kServeSlotHeader, q.q.data(), sizeof(float) * d);
+        R.ticket[slot] = q.ticket;
+        R.t_submit[slot] = q.t_submit;
+        R.collected[slot] = 0;
+        R.tab_end[slot] = tend;
+        R.tab_head = tend;
+        R.published++;
+        S->pending.pop_front();
+        n++;
+    }
+    if (n) {
+        S->inflight = R.published - R.finished;
+        S->max_inflight_seen = std::max(S->max_inflight_seen, S->inflight);
+        S->batched_requests += n;
+        // the slots' contents before the count that publishes them
+        __atomic_store_n(&R.h_ctl[0], (uint64_t)R.published, __ATOMIC_RELEASE);
+    }
+    return n;
+}
+
+// Collect answered slots; returns how many, or -1 when a slot held a wrong
+// sequence word (a broken ring: the server stops).
+int64_t ring_collect(jag_server *S)
+{
+    Ring &R = S->ring;
+    const int k = S->P.k;
+    std::vector<std::pair<uint64_t, Done>> got;
+    int64_t bad = -1;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        const int64_t lo = R.freed, hi = R.published;
+        auto now = clk::now();
+        for (int64_t h = lo; h < hi; h++) {
+            const int64_t slot = h & (R.C - 1);
+            if (R.collected[slot]) continue;
+            if (__atomic_load_n(&R.h_done[slot], __ATOMIC_ACQUIRE) != (uint64_t)h + 1) continue;
+            if (R.h_cnt[slot] < 0) {
+                bad = h;
+                break;
+            }
+            Done r;
+            r.ids.assign(R.h_ids + slot * k, R.h_ids + (slot + 1) * k);
+            r.dists.assign(R.h_d + slot * k, R.h_d + (slot + 1) * k);
+            r.count = R.h_cnt[slot];
+            r.latency_us = std::chrono::duration<double, std::micro>(now - R.t_submit[slot]).count();
+            got.emplace_back(R.ticket[slot], std::move(r));
+            R.collected[slot] = 1;
+        }
+        if (bad >= 0) {
+            char msg[160];
+            std::snprintf(msg, sizeof msg, "request %lld found a wrong sequence word in its ring slot",
+                          (long long)bad);
+            S->error = msg;
+            S->stop = true;
+            S->cv_done.notify_all();
+            return -1;
+        }
+        while (R.freed < R.published && R.collected[R.freed & (R.C - 1)]) {
+            R.tab_tail = std::max(R.tab_tail, R.tab_end[R.freed & (R.C - 1)]);
+            R.freed++;
+        }
+        for (auto &x : got) {
+            S->latencies.push_back(x.second.latency_us);
+            S->done.emplace(x.first, std::move(x.second));
+        }
+        if (!got.empty()) {
+            R.finished += (int64_t)got.size();
+            S->completed += (int64_t)got.size();
+            S->inflight = R.published - R.finished;
+            S->t_last = now;
+            S->cv_done.notify_all();
+        }
+    }
+    return (int64_t)got.size();
+}
+
+void ring_fail(jag_server *S, const char *what, hipError_t e)
+{
+    std::lock_guard<std::mutex> g(S->mu);
+    char msg[256];
+    std::snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+    S->error = msg;
+    S->stop = true;
+    S->cv_done.notify_all();
+}
+
+void ring_loop(jag_server *S)
+{
+    (void)hipSetDevice(S->idx->ix.device);
+    Ring &R = S->ring;
+    auto last_answer = clk::now();
+    for (;;) {
+        bool progressed = false;
+        int64_t published;
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            const int64_t n = ring_publish(S);
+            progressed |= n > 0;
+            published = R.published;
+            if (n > 0 && R.published - n == R.finished) last_answer = clk::now();  // the device was idle
+        }
+        const int64_t got = ring_collect(S);
+        if (got < 0) break;
+        progressed |= got > 0;
+        if (got > 0) last_answer = clk::now();
+        // a search takes milliseconds: requests on the device with no answer
+        // for kServeStallS mean the waves cannot see them; stop with an error
+        // instead of waiting forever
+        if (published > R.finished && clk::now() - last_answer > std::chrono::seconds(kServeStallS)) {
+            char what[96];
+            std::snprintf(what, sizeof what, "resident waves answered nothing for %d s", kServeStallS);
+            ring_fail(S, what, hipErrorLaunchTimeOut);
+            break;
+        }
+        // the waves: find out whether they have ended, start them when needed
+        if (R.running) {
+            hipError_t e = hipEventQuery(R.event);
+            if (e == hipSuccess && S->test_fail_batch > 0 && R.launches == S->test_fail_batch)
+                e = hipErrorLaunchFailure;
+            if (e == hipSuccess) {
+                R.running = false;
+                // every claimed request was answered before its wave ended
+                if (ring_collect(S) < 0) break;
+            } else if (e != hipErrorNotReady) {
+                char what[96];
+                std::snprintf(what, sizeof what, "resident waves (launch %lld) failed on the device",
+                              (long long)R.launches);
+                ring_fail(S, what, e);
+                break;
+            }
+        }
+        if (!R.running) {
+            int64_t finished;
+            {
+                std::lock_guard<std::mutex> g(S->mu);
+                finished = R.finished;
+            }
+            if (published > finished) {
+                bool ok = jag::launch_serve(S->idx->ix, S->P.k, S->P.search, R.view, R.waves, R.stream) == JAG_OK;
+                ok = ok && HIPOK(hipEventRecord(R.event, R.stream));
+                if (!ok) {
+                    std::lock_guard<std::mutex> g(S->mu);
+                    S->error = jag_last_error();
+                    if (S->error.empty()) S->error = "resident waves could not be launched";
+                    S->stop = true;
+                    S->cv_done.notify_all();
+                    break;
+                }
+                R.running = true;
+                R.launches++;
+                std::lock_guard<std::mutex> g(S->mu);
+                S->batches = R.launches;
+                progressed = true;
+            }
+        }
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            const bool idle = S->pending.empty() && R.finished == R.published;
+            if (S->stop && idle) break;
+            if (!progressed) {
+                if (idle)
+                    S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                else {
+                    lk.unlock();
+                    std::this_thread::sleep_for(std::chrono::microseconds(10));
+                }
+            }
+        }
+    }
+    // ask running waves to leave (they also leave by themselves once idle)
+    __atomic_store_n(&R.h_ctl[1], (uint64_t)1, __ATOMIC_RELEASE);
+}
+
 }  // namespace
 
 extern "C" {
@@ -316,9 +649,11 @@ jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_serv
         return JAG_EINVAL;
     }
     *out = nullptr;
-    if (P->k < 1 || P->k > 64 || P->max_batch < 1 || P->max_batch > 4096 || P->n_streams < 1 ||
-        P->n_streams > 8 || P->max_wait_us < 0 || P->max_inflight < 0 || P->queue_capacity < 1 ||
-        P->search.stats || P->search.features || P->search.learned == 2) {
+    const bool slots = P->slot_admission == 1;
+    if (P->k < 1 || P->k > 64 || P->max_inflight < 0 || P->queue_capacity < 1 || P->search.stats ||
+        P->search.features || P->search.learned == 2 || (P->slot_admission != 0 && !slots) || P->reserved ||
+        (!slots && (P->max_batch < 1 || P->max_batch > 4096 || P->n_streams < 1 || P->n_streams > 8 ||
+                    P->max_wait_us < 0))) {
         set_error("bad server parameters");
         return JAG_EINVAL;
     }
@@ -326,6 +661,35 @@ jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_serv
     if (hipSetDevice(ix.device) != hipSuccess) {
         set_error("cannot select device %d", ix.device);
         return JAG_EDEVICE;
+    }
+    if (slots) {
+        int64_t resident = 0;
+        jag_status st = jag::serve_capacity(ix, P->k, P->search, &resident);
+        if (st != JAG_OK) return st;
+        const int64_t waves = P->max_inflight > 0 ? std::min(P->max_inflight, resident) : resident;
+        const int64_t dev_bytes = ring_device_bytes(waves, ix.d);
+        if (P->hbm_budget_bytes > 0 && dev_bytes > P->hbm_budget_bytes) {
+            set_error("server waves need %lld bytes, over the %lld-byte budget", (long long)dev_bytes,
+                      (long long)P->hbm_budget_bytes);
+            return JAG_EUNSUPPORTED;
+        }
+        auto *S = new (std::nothrow) jag_server;
+        if (!S) return JAG_ENOMEM;
+        S->idx = idx;
+        S->P = *P;
+        S->slot_mode = true;
+        S->resident = resident;
+        S->max_inflight = waves;
+        S->device_bytes = dev_bytes;
+        if (const char *fb = std::getenv("JAG_SERVER_TEST_FAIL_BATCH")) S->test_fail_batch = std::atoll(fb);
+        st = alloc_ring(S, waves);
+        if (st != JAG_OK) {
+            delete S;
+            return st;
+        }
+        S->worker = std::thread(ring_loop, S);
+        *out = S;
+        return JAG_OK;
     }
     int64_t resident = 0;
     size_t lds = 0;
@@ -505,6 +869,7 @@ void jag_server_stop(jag_server *S)
         S->cv_work.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
+    if (S->slot_mode) free_ring(S->ring);
     for (auto &s : S->slots) {
         if (s.stream) (void)hipStreamSynchronize(s.stream);
         free_slot(s);

@@ -383,7 +383,8 @@ def jag_predictor_grad(features, targets, params, stream=None):
 class jag_server_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("search", jag_search_params), ("max_batch", C.c_int32),
                 ("n_streams", C.c_int32), ("max_wait_us", C.c_int32), ("max_inflight", C.c_int64),
-                ("queue_capacity", C.c_int64), ("hbm_budget_bytes", C.c_int64)]
+                ("queue_capacity", C.c_int64), ("hbm_budget_bytes", C.c_int64),
+                ("slot_admission", C.c_int32), ("reserved", C.c_int32)]
 
 
 class jag_server_stats(C.Structure):
@@ -438,9 +439,11 @@ class Server:
 
 def jag_server_start(idx: Index, k: int, search: SearchParams, max_batch: int = 1024,
                      n_streams: int = 4, max_wait_us: int = 200, max_inflight: int = 0,
-                     queue_capacity: int = 1 << 22, hbm_budget_bytes: int = 0) -> Server:
+                     queue_capacity: int = 1 << 22, hbm_budget_bytes: int = 0,
+                     slot_admission: bool = False) -> Server:
     p = jag_server_params(int(k), search.c(), int(max_batch), int(n_streams), int(max_wait_us),
-                          int(max_inflight), int(queue_capacity), int(hbm_budget_bytes))
+                          int(max_inflight), int(queue_capacity), int(hbm_budget_bytes),
+                          int(bool(slot_admission)), 0)
     h = C.c_void_p()
     _check(_server_lib().jag_server_start(idx.handle, C.byref(p), C.byref(h)))
     return Server(h, idx, k)

@@ -168,3 +168,36 @@ def test_weight_jag_builds_a_searchable_range_graph():
     r = O.search(w.X, adj, entry, A, w.Q, w.F, w.pool, 128, 10, nthreads=8)
     rec = float(np.nanmean(O.recall_at_k(r.ids, gi, gd, nv, 10)))
     assert rec >= 0.9, rec
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding passes by pointer has the header's size and
+    field offsets (the header compiled by the host C compiler)."""
+    import ctypes as C
+    import json
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    structs = {"jag_search_params": jag.jag_search_params, "jag_index_info": jag.jag_index_info,
+               "jag_server_params": jag.jag_server_params, "jag_server_stats": jag.jag_server_stats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "jag.h"', "int main(void) {",
+             'printf("{");']
+    first = True
+    for name, cls in structs.items():
+        for field, _ in cls._fields_:
+            sep = "" if first else ","
+            first = False
+            lines.append(f'printf("{sep}\\"{name}.{field}\\": %zu", offsetof({name}, {field}));')
+        lines.append(f'printf(",\\"{name}\\": %zu", sizeof({name}));')
+    lines += ['printf("}\\n");', "return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    want = json.loads(subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout)
+    for name, cls in structs.items():
+        assert C.sizeof(cls) == want[name], name
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == want[f"{name}.{field}"], (name, field)
