@@ -602,6 +602,24 @@ class Leg:
         self.stats = torch.zeros((self.nq, 4), dtype=torch.int32, device=dev)
         self.has_valid = self.nv > 0
 
+    def selectivity_accuracy(self) -> dict:
+        """The records' selectivity estimate (a predictor feature) against the
+        exact fraction of valid items (from the oracle's exact answers), over
+        queries with at least one valid item: mean and 90th percentile of
+        |log2(estimate / exact)|, and the correlation of the two logs."""
+        rec = self.rec[id(self.cfg.ix32)].cpu().numpy()
+        est = rec[:, 28:32].copy().view(np.float32)[:, 0].astype(np.float64)
+        ok = self.nv > 0
+        if not ok.any():
+            return None
+        exact = self.nv[ok] / float(self.cfg.w.n)
+        le, lx = np.log2(np.maximum(est[ok], 1e-12)), np.log2(exact)
+        err = np.abs(le - lx)
+        corr = float(np.corrcoef(le, lx)[0, 1]) if np.std(le) > 0 and np.std(lx) > 0 else None
+        return {"queries": int(ok.sum()), "mean_abs_log2_error": round(float(err.mean()), 4),
+                "p90_abs_log2_error": round(float(np.percentile(err, 90)), 4),
+                "log_correlation": corr and round(corr, 4)}
+
     def records(self, ix):
         from paper_2602_10258_amd import jag
         if id(ix) not in self.rec:
@@ -742,7 +760,8 @@ class Leg:
         return dict(kernel_ms=round(kern_ms, 4), kernel_qps=round(self.nq / (kern_ms / 1e3), 1),
                     end_to_end_qps=round(e2e, 1),
                     roofline={"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                              "frac": round(achieved / PEAK_HBM_GBS, 4)},
+                              "frac": round(achieved / PEAK_HBM_GBS, 4),
+                              "gather_ceiling": gather_ceiling(self.cfg, self, st, store, rerank, achieved)},
                     alg_bytes_per_query=round(alg / self.nq, 1), mean_expansions=round(float(st[:, 0].mean()), 2),
                     mean_distance_computations=round(float(st[:, 1].mean()), 2),
                     mean_attribute_evaluations=round(float(st[:, 2].mean()), 2))
@@ -825,6 +844,7 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
            "learned_over_bf16_fixed": (best_l and best_16 and round(best_l["qps"] / best_16["qps"], 4)) or None,
            "learned_ladder": None if lad is None else lad.tolist(),
            "predictor": rep and rep.__dict__,
+           "selectivity_estimate": leg.selectivity_accuracy(),
            "graph_build_seconds": cfg.build_times,
            "sweeps": {"fp32_fixed": [rounded(r) for r in fixed], "bf16_rerank_fixed": [rounded(r) for r in fixed16],
                       "fp8_rerank_fixed": [rounded(r) for r in fixed8], "learned": [rounded(r) for r in learned]}}
@@ -1069,6 +1089,46 @@ def main():
     print(json.dumps(out, default=float), flush=True)
 
 
+def _search_stride(raw: int) -> int:
+    """Row stride the search kernels use for rows of `raw` bytes: 64-byte
+    padding, then a multiple of 16 bytes per lane of the row's lane group."""
+    stride = (raw + 63) // 64 * 64
+    g = 4 if stride <= 384 else 8 if stride <= 512 else 16
+    return (stride + 16 * g - 1) // (16 * g) * (16 * g)
+
+
+def gather_ceiling(cfg, leg, st, store, rerank, achieved):
+    """The device's rate for reading rows at random, data-dependent indices
+    (jag_gather_ceiling, 5,120 waves as the search keeps resident, 1 GiB
+    buffer) at the three row sizes of this search -- adjacency rows, store
+    rows, FP32 rerank rows -- and the rate the search's algorithmic bytes
+    would reach if each of the three streams ran at its row size's rate."""
+    from paper_2602_10258_amd import jag
+    torch, w = cfg.torch, cfg.w
+    info = cfg.ix32.info()
+    up4 = lambda x: (x + 3) // 4 * 4  # noqa: E731
+    scal = up4(w.R) if info.has_scalar else 0
+    lab = up4(scal + w.R if info.has_scalar else w.R) if info.has_labels else 0
+    words = up4(lab + w.R * (info.label_width // 2) if info.has_labels else (scal + w.R if info.has_scalar else w.R))
+    sizes = {"adjacency": _search_stride(4 * words), "store": _search_stride(row_bytes(w.d, store)),
+             "rerank": _search_stride(4 * w.d)}
+    buf = torch.empty(1 << 30, dtype=torch.uint8, device=cfg.dev)
+    rates = {}
+    for name, b in sizes.items():
+        if b not in rates:
+            rates[b] = jag.jag_gather_ceiling(buf, b, waves=256 * 20, iters=200, reps=5)
+    del buf
+    parts = {"adjacency": float((st[:, 0] * 4 * w.R + st[:, 2] * attr_bytes(w, leg.ftype)).sum()),
+             "store": float((st[:, 1] * row_bytes(w.d, store) + 4 * w.d + 128 + 8 * leg.k + 4).sum()),
+             "rerank": float(len(st) * 4 * leg.k * 4 * w.d) if rerank else 0.0}
+    total = sum(parts.values())
+    mix = total / sum(parts[n] / rates[sizes[n]] for n in parts if parts[n] > 0)
+    return {"unit": "GB/s", "row_bytes": sizes, "rate_by_row_bytes": {str(b): round(r, 1) for b, r in rates.items()},
+            "mix": round(mix, 1), "frac_of_mix": round(achieved / mix, 4),
+            "note": "random rows at data-dependent indices, 5,120 one-wave workgroups; the mix weighs each "
+                    "row size by the search's algorithmic bytes of that stream"}
+
+
 def timed_steps(args, cfg, hout, op):
     """The headline leg's operating point: `warmup` untimed steps, then `steps`
     timed ones (HIP events on the search stream, wall clock around all of them),
@@ -1100,7 +1160,8 @@ def timed_steps(args, cfg, hout, op):
     st = leg.stats.cpu().numpy().astype(np.int64)
     achieved = leg.alg_bytes(st, op["store"], op["rerank"]) / (kern_ms / 1e3) / 1e9
     hout["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(cfg.name, op["name"])}
+                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(cfg.name, op["name"]),
+                        "gather_ceiling": gather_ceiling(cfg, leg, st, op["store"], op["rerank"], achieved)}
     out = {"op": {k_: op[k_] for k_ in ("mode", "store", "rerank", "name")},
            "value": round(leg.nq / (ms_per_step / 1e3), 1), "ms_per_step": round(ms_per_step, 4),
            "kernel_ms": round(kern_ms, 4), "recall": round(rec, 4)}

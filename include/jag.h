@@ -480,6 +480,25 @@ jag_status jag_server_stats_get(jag_server *s, jag_server_stats *out);
 /* Drain, stop the scheduler and free the server.  NULL is allowed. */
 void jag_server_stop(jag_server *s);
 
+/* ---- measurement (not in the paper) ---------------------------------------- */
+
+/*
+ * The device's throughput for the access pattern the search lives on: rows
+ * of row_bytes bytes read at random row indices.  `waves` one-wave workgroups
+ * each read `iters` rows per group of G lanes (G = 4 for rows of up to 384
+ * bytes, 8 up to 512, 16 beyond, as the search does), 16 bytes per lane per
+ * load; every row index depends on the data of the group's previous row, as
+ * the next expansion of a search depends on the last.  buffer: device
+ * memory of buffer_bytes bytes (its contents are read, never written; use
+ * far more than the last-level cache, e.g. 1 GiB); row_bytes: 64..1024, a
+ * multiple of 64; waves: 1..2^20; iters: 1..100000.  The kernel runs once
+ * untimed, then `reps` (1..100) times between events on `stream`; the call
+ * waits for them and returns the mean rate in *gbs_out (10^9 bytes/s of rows
+ * read).  Errors: EINVAL (bad sizes, NULL), EDEVICE.
+ */
+jag_status jag_gather_ceiling(const void *buffer, int64_t buffer_bytes, int32_t row_bytes, int32_t waves,
+                              int32_t iters, int32_t reps, void *stream, double *gbs_out);
+
 /* ---- misc ---------------------------------------------------------------- */
 
 const char *jag_last_error(void);

@@ -101,6 +101,7 @@ def lib():
             "jag_set_predictor": ([P, P, i32, P, f32], i32),
             "jag_train_predictor": ([P, P, i64, P, i32, i32, f32, u64, P, P], i32),
             "jag_predictor_grad": ([P, P, i64, P, P, P, P], i32),
+            "jag_gather_ceiling": ([P, i64, i32, i32, i32, i32, P, P], i32),
             "jag_last_error": ([], C.c_char_p),
             "jag_version": ([], C.c_char_p),
         }
@@ -117,7 +118,7 @@ def exported_symbols() -> list[str]:
             "jag_get_graph", "jag_get_store", "jag_encode_filters", "jag_encoded_bytes",
             "jag_encode_filters_sized", "jag_search_encoded", "jag_search_encoded_noalloc",
             "jag_search_batch", "jag_exact_knn", "jag_set_predictor", "jag_train_predictor",
-            "jag_predictor_grad", "jag_last_error", "jag_version", "jag_server_start",
+            "jag_predictor_grad", "jag_gather_ceiling", "jag_last_error", "jag_version", "jag_server_start",
             "jag_server_submit", "jag_server_poll", "jag_server_drain", "jag_server_stats_get",
             "jag_server_stop"]
 
@@ -350,6 +351,14 @@ def jag_search_batch(idx: Index, Q, F, pool, k: int, params: SearchParams, ids, 
 def jag_exact_knn(idx: Index, Q, records, k: int, ids, dists, count, stream=None):
     _check(lib().jag_exact_knn(idx.handle, _ptr(Q), Q.shape[0], _ptr(records), int(k), _ptr(ids),
                                _ptr(dists), _ptr(count), _stream(stream)))
+
+
+def jag_gather_ceiling(buffer, row_bytes: int, waves: int, iters: int, reps: int = 5, stream=None) -> float:
+    """Random row-gather throughput (GB/s) over a device buffer (torch tensor)."""
+    gbs = C.c_double()
+    _check(lib().jag_gather_ceiling(_ptr(buffer), buffer.numel() * buffer.element_size(), int(row_bytes),
+                                    int(waves), int(iters), int(reps), _stream(stream), C.byref(gbs)))
+    return float(gbs.value)
 
 
 def jag_set_predictor(idx: Index, params, ladder, rho: float):

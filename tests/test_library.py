@@ -201,3 +201,17 @@ def test_binding_structs_match_the_header(tmp_path):
         assert C.sizeof(cls) == want[name], name
         for field, _ in cls._fields_:
             assert getattr(cls, field).offset == want[f"{name}.{field}"], (name, field)
+
+
+def test_gather_ceiling_rejects_bad_arguments():
+    """Argument checks happen before any device call (no GPU needed)."""
+    import ctypes as C
+    L = jag.lib()
+    out = C.c_double(-1.0)
+    fake = C.c_void_p(4096)  # never dereferenced: the checks fail first
+    for args in [(None, 1 << 30, 192, 64, 10, 1), (fake, 1 << 30, 100, 64, 10, 1), (fake, 1 << 30, 192, 0, 10, 1),
+                 (fake, 1 << 30, 192, 64, 0, 1), (fake, 1 << 30, 192, 64, 10, 0), (fake, 1000, 192, 64, 10, 1),
+                 (fake, 1 << 30, 448, 64, 10, 1)]:  # 448 is no multiple of 8 lanes x 16 bytes
+        st = L.jag_gather_ceiling(args[0], *args[1:], None, C.byref(out))
+        assert st == jag.JAG_EINVAL, args
+    assert out.value == -1.0
