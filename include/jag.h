@@ -490,8 +490,9 @@ void jag_server_stop(jag_server *s);
  * load; every row index depends on the data of the group's previous row, as
  * the next expansion of a search depends on the last.  buffer: device
  * memory of buffer_bytes bytes (its contents are read, never written; use
- * far more than the last-level cache, e.g. 1 GiB); row_bytes: 64..1024, a
- * multiple of 64; waves: 1..2^20; iters: 1..100000.  The kernel runs once
+ * far more than the last-level cache, e.g. 1 GiB); row_bytes: 64..16384, a
+ * multiple of 64 and of 16 bytes per lane (128 for rows of 385..512 bytes, 256
+ * beyond); waves: 1..2^20; iters: 1..100000.  The kernel runs once
  * untimed, then `reps` (1..100) times between events on `stream`; the call
  * waits for them and returns the mean rate in *gbs_out (10^9 bytes/s of rows
  * read).  Errors: EINVAL (bad sizes, NULL), EDEVICE.

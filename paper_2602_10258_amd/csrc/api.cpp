@@ -17,6 +17,10 @@
 
 #include "jag_internal.h"
 
+#if defined(__AVX2__)
+#include <immintrin.h>
+#endif
+
 namespace jag {
 
 static thread_local char g_err[512] = "";
@@ -165,6 +169,54 @@ double label_freq(const Index &ix, int32_t l)
 }  // namespace
 
 // Encode queries [q0, q1); stops at the first bad filter (message via set_error).
+// Distance table of a Boolean function of nv variables (Section 3.1): on
+// entry D[x] = 0 where the function is true and 255 elsewhere; on exit D[x]
+// is the fewest variable flips from assignment x to a true assignment (255:
+// none).  Hamming distance is a sum over the variables, so one min-plus pass
+// per variable, D[x] = min(D[x], D[x ^ 2^v] + 1), in any order of the
+// variables, gives the exact transform.  Variables 0..4 stay inside each
+// 32-byte block and take one byte shuffle per pass; the others pair
+// contiguous runs.
+static void distance_transform(uint8_t *D, int nv)
+{
+    const int N = 1 << nv;
+    int v = 0;
+#if defined(__AVX2__)
+    if (nv >= 5) {
+        const __m256i one = _mm256_set1_epi8(1);
+        __m256i swap[4];
+        for (int k = 0; k < 4; k++) {
+            alignas(32) uint8_t idx[32];
+            for (int i = 0; i < 32; i++) idx[i] = (uint8_t)((i ^ (1 << k)) & 15);
+            swap[k] = _mm256_load_si256(reinterpret_cast<const __m256i *>(idx));
+        }
+        for (int base = 0; base < N; base += 32) {
+            __m256i d = _mm256_loadu_si256(reinterpret_cast<const __m256i *>(D + base));
+            for (int k = 0; k < 4; k++)  // partners 1, 2, 4, 8 bytes away (inside 16-byte lanes)
+                d = _mm256_min_epu8(d, _mm256_adds_epu8(_mm256_shuffle_epi8(d, swap[k]), one));
+            // partner 16 bytes away: the other 16-byte lane
+            d = _mm256_min_epu8(d, _mm256_adds_epu8(_mm256_permute2x128_si256(d, d, 1), one));
+            _mm256_storeu_si256(reinterpret_cast<__m256i *>(D + base), d);
+        }
+        v = 5;
+    }
+#endif
+    for (; v < nv; v++) {
+        const int b = 1 << v;
+        for (int base = 0; base < N; base += 2 * b) {
+            uint8_t *__restrict lo = D + base;
+            uint8_t *__restrict hi = D + base + b;
+            for (int i = 0; i < b; i++) {
+                const uint8_t d0 = lo[i], d1 = hi[i];
+                const uint8_t a0 = d0 == 255 ? 255 : (uint8_t)(d0 + 1);
+                const uint8_t a1 = d1 == 255 ? 255 : (uint8_t)(d1 + 1);
+                lo[i] = d0 < a1 ? d0 : a1;
+                hi[i] = d1 < a0 ? d1 : a0;
+            }
+        }
+    }
+}
+
 // TABLE filters write their distance table at tab_base + tpos[q] (tab_base is
 // also the address of record 0); without a table area they are rejected.
 static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0, int64_t q1,
@@ -367,17 +419,7 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
             uint8_t *D = tab_base + tpos[q];
             const int N = 1 << nv;
             for (int x = 0; x < N; x++) D[x] = ((w[x >> 5] >> (x & 31)) & 1u) ? 0 : 255;
-            // Hamming distance is a sum over variables, so one min-plus pass
-            // per variable gives the exact distance transform
-            for (int v = 0; v < nv; v++) {
-                const int b = 1 << v;
-                for (int x = 0; x < N; x++)
-                    if (!(x & b)) {
-                        int d0 = D[x], d1 = D[x | b];
-                        D[x] = (uint8_t)std::min(d0, std::min(d1 + 1, 255));
-                        D[x | b] = (uint8_t)std::min(d1, std::min(d0 + 1, 255));
-                    }
-            }
+            distance_transform(D, nv);
             // probability of each assignment under independent labels, built
             // by doubling (each product is formed in variable order, as a
             // per-assignment loop would), summed over the true assignments
@@ -386,14 +428,19 @@ static jag_status encode_range(const Index &ix, const jag_filter *F, int64_t q0,
             for (int v = 0; v < nv; v++) {
                 const double pf = label_freq(ix, r.lits[v]);
                 const int b = 1 << v;
+                double *__restrict lo = pa.data();
+                double *__restrict hi = pa.data() + b;
                 for (int x = 0; x < b; x++) {
-                    pa[(size_t)(x | b)] = pa[(size_t)x] * pf;
-                    pa[(size_t)x] = pa[(size_t)x] * (1.0 - pf);
+                    hi[x] = lo[x] * pf;
+                    lo[x] = lo[x] * (1.0 - pf);
                 }
             }
+            // in increasing order of the true assignments, visiting set bits only
             sel = 0.0;
-            for (int x = 0; x < N; x++)
-                if ((w[x >> 5] >> (x & 31)) & 1u) sel += pa[(size_t)x];
+            for (int wi = 0; wi < (N + 31) / 32; wi++) {
+                uint32_t word = N >= 32 ? w[wi] : (w[wi] & ((1u << N) - 1u));
+                for (; word; word &= word - 1) sel += pa[(size_t)(wi * 32 + __builtin_ctz(word))];
+            }
             sel = std::min(1.0, sel);
             r.table_off = tpos[q] - q * (int64_t)sizeof(FilterRecord);
         } else {

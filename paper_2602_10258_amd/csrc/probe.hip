@@ -53,7 +53,7 @@ extern "C" jag_status jag_gather_ceiling(const void *buffer, int64_t buffer_byte
                                          double *gbs_out)
 {
     using namespace jag;
-    if (!buffer || !gbs_out || row_bytes < 64 || row_bytes > 1024 || row_bytes % 64 || waves < 1 ||
+    if (!buffer || !gbs_out || row_bytes < 64 || row_bytes > 16384 || row_bytes % 64 || waves < 1 ||
         waves > (1 << 20) || iters < 1 || iters > 100000 || reps < 1 || reps > 100 ||
         buffer_bytes < 64 * (int64_t)row_bytes || buffer_bytes / row_bytes > (int64_t)UINT32_MAX) {
         set_error("jag_gather_ceiling: bad arguments");
