@@ -454,6 +454,63 @@ __device__ __forceinline__ int merge_small(const Lds &s, int cnt, int ls, bool h
     return nc < ls ? nc : ls;
 }
 
+// Merge of at most kSmallMerge survivors whose insertion positions pos (the
+// number of list entries ahead of them) are known, into a list of any
+// length: each survivor's rank among the survivors comes from a readlane
+// loop (no LDS round trips); the positions go to spos in rank order (so they
+// are non-decreasing), padded to eight with INT_MAX; a list entry at j then
+// moves down by the number of survivors with position <= j, counted against
+// the eight positions read with two 16-byte LDS loads, instead of a binary
+// search over the survivors' keys per entry.  A survivor lands at pos + rank.
+__device__ __forceinline__ int merge_few(const Lds &s, int cnt, int ls, bool have, uint64_t ck, uint32_t ci,
+                                         int pos, uint64_t vm, int mv, int *minpos)
+{
+    const int lane = threadIdx.x;
+    int rank = 0;
+    for (uint64_t mm = vm; mm; mm &= mm - 1) {
+        const int d = __builtin_ctzll(mm);
+        const uint32_t dkh = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(ck >> 32), d);
+        const uint32_t dkl = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ck, d);
+        const uint32_t di = (uint32_t)__builtin_amdgcn_readlane((int)ci, d);
+        const uint64_t dk = ((uint64_t)dkh << 32) | dkl;
+        rank += (have && key_lt(dk, di, ck, ci)) ? 1 : 0;
+    }
+    if (have) s.spos[rank] = pos;
+    if (lane >= mv && lane < kSmallMerge) s.spos[lane] = INT_MAX;
+    __syncthreads();
+    const int4 pa = *reinterpret_cast<const int4 *>(s.spos);
+    const int4 pb = *reinterpret_cast<const int4 *>(s.spos + 4);
+    const int mp = pa.x;
+    const int newcnt = cnt + mv < ls ? cnt + mv : ls;
+    // shift list entries from the end, chunk by chunk, so no unread entry is overwritten
+    const int top = ((cnt - 1) >> 6) << 6;
+    for (int j0 = top; j0 >= (mp & ~63); j0 -= 64) {
+        const int j = j0 + lane;
+        const bool move = j < cnt && j >= mp;
+        uint64_t kj = 0;
+        uint32_t ij = 0;
+        if (move) {
+            kj = s.key[j];
+            ij = s.idf[j];
+        }
+        const int sh = (pa.x <= j) + (pa.y <= j) + (pa.z <= j) + (pa.w <= j) + (pb.x <= j) + (pb.y <= j) +
+                       (pb.z <= j) + (pb.w <= j);
+        __syncthreads();
+        if (move && j + sh < ls) {
+            s.key[j + sh] = kj;
+            s.idf[j + sh] = ij;
+        }
+        __syncthreads();
+    }
+    if (have && pos + rank < ls) {
+        s.key[pos + rank] = ck;
+        s.idf[pos + rank] = ci;
+    }
+    __syncthreads();
+    *minpos = mp;
+    return newcnt;
+}
+
 // Merge candidates (lane c < m holds cid/cdf/cd2 slot c) into the sorted
 // list of cnt entries, keeping at most ls.  Returns the new size; *minpos is
 // the list position of the best inserted candidate (ls if none).
@@ -497,6 +554,7 @@ __device__ int merge_candidates(const Lds &s, int m, int cnt, int ls, int *minpo
         *minpos = ls;
         return cnt;
     }
+    if (mv <= kSmallMerge) return merge_few(s, cnt, ls, have, ck, ci, pos, vm, mv, minpos);
     // rank among the surviving candidates (written compacted to skey/sid first)
     int slot = lanes_below(vm);
     if (have) {
@@ -528,13 +586,14 @@ __device__ int merge_candidates(const Lds &s, int m, int cnt, int ls, int *minpo
             kj = s.key[j];
             ij = s.idf[j];
         }
+        // survivors ahead of entry j: those inserted at a position <= j
+        // (spos is in rank order, so non-decreasing)
         int sh = 0;
         if (mv_) {
             int lo = 0, hi = mv;
-            uint32_t id = ij & kIdMask;
             while (lo < hi) {
                 int mid = (lo + hi) >> 1;
-                if (key_lt(s.skey[mid], s.sid[mid], kj, id)) lo = mid + 1;
+                if (s.spos[mid] <= j) lo = mid + 1;
                 else hi = mid;
             }
             sh = lo;
