@@ -237,20 +237,30 @@ def parse_thresholds(text: str):
     return out
 
 
+KERNEL_SOURCES = ("search_device.h", "search.hip")
+
+
+def kernel_source_sha1() -> str:
+    """sha1 over the search kernel's sources (the device code, then its launches)."""
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2602_10258_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload: str, op_name: str):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     summaries (one entry, or a list of entries, one per operating point),
     only if taken on this exact kernel source and operating point;
     otherwise None."""
-    import hashlib
     p = os.path.join(ROOT, "profiles", f"search_kernel_{workload}_counters.json")
-    src = os.path.join(ROOT, "paper_2602_10258_amd", "csrc", "search.hip")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_sha1()
     for e in d if isinstance(d, list) else [d]:
-        if e.get("search_hip_sha1") == sha and e.get("operating_point") == op_name:
+        if e.get("kernel_source_sha1") == sha and e.get("operating_point") == op_name:
             return e["traffic_bytes_per_launch"]
     return None
 
