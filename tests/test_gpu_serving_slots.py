@@ -205,3 +205,43 @@ def test_slots_failed_launch_stops_the_server(mixed_world, monkeypatch):
     finally:
         jag.jag_server_stop(s)
     _say("failed launch reported, server stopped")
+
+
+def test_slots_ring_wraps_with_few_waves(mixed_world):
+    """Eight waves and 3,200 requests: the 1,024-slot ring is reused three
+    times over (a slot is written again only after its answer was
+    collected), and every answer is the direct search's."""
+    w, A, adj, entry = mixed_world
+    idx = _index(w, adj, entry)
+    ref = gpu_search(idx, w.Q, w.F, w.pool, 10, 32)
+    s = jag.jag_server_start(idx, 10, jag.SearchParams(L=32), slot_admission=True, max_inflight=8)
+    try:
+        t = jag.jag_server_submit(s, np.tile(w.Q, (20, 1)), np.tile(w.F, (20, 1)), w.pool)
+        jag.jag_server_drain(s)
+        res = _collect(s, t)
+        st = jag.jag_server_stats_get(s)
+    finally:
+        jag.jag_server_stop(s)
+    _same(res, ref, np.tile(np.arange(w.nq), 20))
+    assert st["completed"] == 20 * w.nq and st["max_inflight_seen"] <= 1024
+    _say("ring reused:", {k: st[k] for k in ("batches", "max_inflight_seen", "p99_us")})
+
+
+def test_slots_table_area_wraps_with_wide_tables():
+    """Fifteen-variable tables (32 KiB each) in numbers that overflow the
+    server's 8 MiB host table area: publishing waits for answered requests to
+    free their tables, the area wraps around, and every answer is the direct
+    search's."""
+    from .test_gpu_table_filters import _bool_world
+    w, A, adj, entry = _bool_world(15, nq=24)
+    idx = jag.jag_build_from_graph(w.X, adj, entry, label_off=w.loff, labels=w.lab, vocab=w.vocab)
+    ref = gpu_search(idx, w.Q, w.F, w.pool, 10, 48)
+    reps = 40  # 960 tables, 30 MiB
+    F = np.tile(w.F, (reps, 1))
+    _say("wide tables through the slot server:", F.shape[0])
+    s = jag.jag_server_start(idx, 10, jag.SearchParams(L=48), slot_admission=True)
+    try:
+        res = _collect(s, jag.jag_server_submit(s, np.tile(w.Q, (reps, 1)), F, w.pool), timeout=120.0)
+    finally:
+        jag.jag_server_stop(s)
+    _same(res, ref, np.tile(np.arange(w.nq), reps))
