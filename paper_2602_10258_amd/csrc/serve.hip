@@ -666,6 +666,10 @@ jag_status jag_server_start(jag_index *idx, const jag_server_params *P, jag_serv
         int64_t resident = 0;
         jag_status st = jag::serve_capacity(ix, P->k, P->search, &resident);
         if (st != JAG_OK) return st;
+        if (resident < 1) {
+            set_error("no serving wave fits on a compute unit with this search's LDS");
+            return JAG_EUNSUPPORTED;
+        }
         const int64_t waves = P->max_inflight > 0 ? std::min(P->max_inflight, resident) : resident;
         const int64_t dev_bytes = ring_device_bytes(waves, ix.d);
         if (P->hbm_budget_bytes > 0 && dev_bytes > P->hbm_budget_bytes) {
