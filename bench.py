@@ -88,6 +88,8 @@ def parse():
     ap.add_argument("--op-mode", default="fp32-fixed",
                     choices=["fp32-fixed", "bf16+rerank-fixed", "fp8+rerank-fixed", "learned+bf16+rerank"])
     ap.add_argument("--delta", type=float, default=0.0)
+    ap.add_argument("--single-pass", action="store_true",
+                    help="profile mode, learned: the one-pass schedule (prediction inside the search)")
     ap.add_argument("--ladder", default=None,
                     help="profile mode, learned: comma-separated ladder (as the bench line reports it)")
     ap.add_argument("--ladder-top", type=int, default=None,
@@ -844,10 +846,27 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
     best_16, interp_16 = at95(fixed16)
     best_8, interp_8 = at95(fixed8) if fixed8 else (None, None)
     best_l, interp_l = at95(learned) if learned else (None, None)
+    schedules = None
+    if best_l:
+        # the sweep runs the two-pass schedule (predict, order by predicted
+        # beam, resume); at the chosen offset the one-pass schedule (the
+        # prediction taken inside each search, launch order by selectivity
+        # class) finds the same ids and may be faster where beams vary little
+        one = leg.point(cfg.ix16, jag.SearchParams(L=leg.k, learned=1, delta=best_l["delta"], rerank_mult=4,
+                                                   single_pass=1))
+        one["delta"] = best_l["delta"]
+        schedules = {"two_pass_qps": round(best_l["qps"], 1), "one_pass_qps": round(one["qps"], 1),
+                     "one_pass_recall": round(one["recall"], 4)}
+        log(f"{leg.tag()} learned at delta={best_l['delta']:g}: two-pass {best_l['qps']:.0f} qps, "
+            f"one-pass {one['qps']:.0f} qps (recall {one['recall']:.4f})")
+        if one["recall"] >= 0.95 and one["qps"] > best_l["qps"]:
+            one["single_pass"] = 1
+            best_l = one
     cands = []
     if best_l:
-        cands.append(("learned+bf16+rerank", cfg.ix16, jag.SearchParams(L=leg.k, learned=1, delta=best_l["delta"],
-                                                                        rerank_mult=4), 1, True, best_l))
+        cands.append(("learned+bf16+rerank" + (" one-pass" if best_l.get("single_pass") else ""), cfg.ix16,
+                      jag.SearchParams(L=leg.k, learned=1, delta=best_l["delta"], rerank_mult=4,
+                                       single_pass=best_l.get("single_pass", 0)), 1, True, best_l))
     if best_16:
         cands.append(("bf16+rerank-fixed", cfg.ix16, jag.SearchParams(L=best_16["L"], rerank_mult=4), 1, True,
                       best_16))
@@ -865,6 +884,7 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
                "learned_bf16_rerank": best_l and round(best_l["qps"], 1),
                "learned_bf16_rerank_interp": interp_l and round(interp_l, 1),
                "learned_delta": best_l and best_l["delta"], "learned_mean_beam": best_l and round(best_l["lhat"], 2)},
+           "learned_schedules": schedules,
            "learned_over_fp32_fixed": (best_l and best_f and round(best_l["qps"] / best_f["qps"], 4)) or None,
            "learned_over_bf16_fixed": (best_l and best_16 and round(best_l["qps"] / best_16["qps"], 4)) or None,
            "learned_ladder": None if lad is None else lad.tolist(),
@@ -955,7 +975,12 @@ def predictor_eval(args, dev, timer):
             if r["recall"] >= 0.95:
                 break
         b32, b16, bl = at95(f32)[0], at95(f16)[0], at95(lr)[0]
+        one = None
+        if bl:  # the one-pass schedule at the same offset (same ids)
+            one = leg.point(ix16, jag.SearchParams(L=w.k, learned=1, delta=bl["delta"], rerank_mult=4,
+                                                   single_pass=1))
         legq[FILTER_NAMES[ft]] = {
+            "learned_one_pass_qps": one and round(one["qps"], 1),
             "fp32_fixed": b32 and {"L": b32["L"], "qps": round(b32["qps"], 1), "expansions": round(b32["hops"], 2)},
             "bf16_rerank_fixed": b16 and {"L": b16["L"], "qps": round(b16["qps"], 1),
                                           "expansions": round(b16["hops"], 2)},
@@ -997,7 +1022,8 @@ def profile_main(args, dev):
         lad = (np.array([int(x) for x in args.ladder.split(",")], dtype=np.int32) if args.ladder
                else learned_ladder(None))
         pred.fit(ix, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4, ladder=lad)
-        sp = jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4)
+        sp = jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4,
+                              single_pass=1 if args.single_pass else 0)
     else:
         sp = jag.SearchParams(L=args.L, rerank_mult=0 if store == jag.STORE_F32 else 4)
     Qd = torch.from_numpy(w.Q).to(dev)

@@ -186,7 +186,10 @@ typedef struct {
                             stream) for each query's saved state: (8 + 3*W + 2) * 4
                             bytes, W = list width (64 or the widest beam, rounded up
                             to 64; 0.8 KB at W = 64); batches needing more than
-                            512 MiB run in chunks. */
+                            512 MiB run in chunks.  Which is faster depends on how
+                            much the predicted beams spread: measured, one launch on
+                            a range workload (ladder to 64), two on label-set
+                            workloads (ladders to 512). */
 } jag_search_params;
 
 typedef struct {
