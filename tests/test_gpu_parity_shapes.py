@@ -161,3 +161,28 @@ def test_trace_features_match_oracle(c1_small, mixed_world, world):
     np.testing.assert_allclose(gf[:, 4], of[:, 4], rtol=0, atol=2e-7)
     np.testing.assert_allclose(gf[:, 5:9], of[:, 5:9], rtol=1e-5, atol=1e-9)
     _say(f"{world}: features of {ok.sum()} queries equal the oracle's")
+
+
+def test_slot_server_on_the_serving_shape(c5_shape):
+    """The resident serving waves at the serving shard's shape (FP8 rows of
+    d = 100, two chunks per lane, scalar and label attributes, all four
+    filter types, FP32 rerank): every answer equals the direct search's and,
+    through it, the contract-mode oracle's."""
+    from .test_gpu_serving import _collect
+    w, A, adj, entry = c5_shape
+    idx = _index(w, adj, entry, jag.STORE_FP8_E4M3, keep_f32=True)
+    sp = jag.SearchParams(L=64, rerank_mult=4)
+    ref = gpu_search(idx, w.Q, w.F, w.pool, 10, 64, rerank_mult=4)
+    base = O.fp8_decode_rows(*O.fp8_encode_rows(w.X))
+    orc = O.search(base, adj, entry, A, w.Q, w.F, w.pool, 64, 10, rerank=w.X, rerank_mult=4, nthreads=8,
+                   contract=lane_order(jag.STORE_FP8_E4M3, w.d))
+    compare_strict(ref["ids"], ref["d2"], ref["count"], orc, "fp8 d=100 L=64 (contract)")
+    s = jag.jag_server_start(idx, 10, sp, slot_admission=True)
+    try:
+        res = _collect(s, jag.jag_server_submit(s, w.Q, w.F, w.pool))
+    finally:
+        jag.jag_server_stop(s)
+    for q, (ids, d, c, lat) in enumerate(res):
+        assert c == ref["count"][q] and np.array_equal(ids, ref["ids"][q]), q
+        assert np.array_equal(d.view(np.uint32), ref["d2"][q].view(np.uint32)), q
+    _say("slot server on the serving shape:", len(res), "answers equal")
