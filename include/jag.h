@@ -168,10 +168,11 @@ typedef struct {
     int32_t *stats;      /* optional device int32 [nq][4]: expansions, vector distances,
                             attribute evaluations, chosen beam (learned) or L */
     float *features;     /* learned == 2: device float [nq][16] predictor features */
-    int32_t hash_log2;   /* 0 = automatic; else 10..13: the per-query LDS table of
-                            discovered ids has 2^hash_log2 slots.  It only trades LDS
-                            (occupancy) against repeated evaluations; results do not
-                            depend on it. */
+    int32_t hash_log2;   /* 0 = automatic (2^10 slots for lists of up to 128 entries,
+                            2^9 for longer ones); else 8..13: the per-query LDS table
+                            of discovered ids has 2^hash_log2 slots.  It only trades
+                            LDS (occupancy) against repeated evaluations; results do
+                            not depend on it. */
     int32_t single_pass; /* learned == 1 only.  0 = two launches: the first runs every
                             query to its prediction point and saves its list and
                             counters; the second resumes the saved searches in order

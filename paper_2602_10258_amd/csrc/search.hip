@@ -344,12 +344,21 @@ ExactFn exact_for_ch(int ch)
     return nullptr;
 }
 
-// Seen-table slots.  The kernel holds at most 4 waves per SIMD (16 per CU)
+// Seen-table slots.  The kernel holds at most 5 waves per SIMD (20 per CU)
 // by registers; 2^10 slots keep LDS from lowering that for lists up to 128
-// entries.  Measured on the range workload (1M x 96, 10k queries): equal to
-// 2^11 at fixed L = 44 and 64 (6-9 % more repeated evaluations, 14 % more
-// resident queries), 17-20 % faster for learned beams (128-entry list).
+// entries.  Longer lists take 2^9 slots: the LDS a wave needs (12 bytes per
+// list entry, 4 per slot, 2.4 KB of staging) then lets more of them share a
+// compute unit, which pays more than the extra evaluations of vertices the
+// smaller table forgets.  Measured on the label-set workload (1M x 128,
+// BF16 + rerank; results do not depend on the table): Boolean filters at
+// L = 192 2.06 M -> 2.58 M queries/s, their learned beam (one pass) 2.45 M
+// -> 2.69 M; subset filters' learned beam (two passes, lists of 512)
+// 0.985 M -> 1.046 M; 2^8 slots were slower than 2^9, 2^11 slower than
+// 2^10.  On the range workload (lists of 64) the occupancy is bound by
+// registers either way and the larger table forgets less.
 constexpr int kDefaultHash = 1024;
+constexpr int kLongListHash = 512;
+constexpr int kLongList = 128;
 // Smallest list width of the first four expansions in learned and trace
 // modes (the widest ladder beam, or L in trace mode, if larger).
 constexpr int kWarmWidth = 64;
@@ -573,9 +582,9 @@ jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void *record
 {
     if (k < 1 || k > 64 || S.L < k || S.L > 1024 || S.learned < 0 || S.learned > 2 ||
         S.rerank_mult < 0 || S.rerank_mult * k > 64 || S.max_hops < 0 || nq > INT_MAX ||
-        (S.hash_log2 != 0 && (S.hash_log2 < 10 || S.hash_log2 > 13))) {
+        (S.hash_log2 != 0 && (S.hash_log2 < 8 || S.hash_log2 > 13))) {
         set_error("need 1 <= k <= 64, k <= L <= 1024, learned in {0,1,2}, rerank_mult*k <= 64, "
-                  "hash_log2 in {0, 10..13}");
+                  "hash_log2 in {0, 8..13}");
         return JAG_EINVAL;
     }
     if (S.rerank_mult > 0 && !ix.d_f32) {
@@ -624,7 +633,7 @@ jag_status plan_search(Index &ix, const float *Q, int64_t nq, const void *record
     if (S.learned != 0 && Lcap < kWarmWidth) Lcap = kWarmWidth;
     a.warm = Lcap;
     Lcap = (Lcap + 63) / 64 * 64;
-    int H = S.hash_log2 ? (1 << S.hash_log2) : kDefaultHash;
+    int H = S.hash_log2 ? (1 << S.hash_log2) : Lcap > kLongList ? kLongListHash : kDefaultHash;
     a.Lcap = Lcap;
     a.Hmask = H - 1;
     ak = ix.has_scalar && !ix.has_labels ? AK_SCALAR : !ix.has_scalar && ix.has_labels ? AK_LABELS : AK_ANY;
