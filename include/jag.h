@@ -349,9 +349,11 @@ jag_status jag_search_encoded_noalloc(jag_index *idx, const float *Q, int64_t nq
                                       int32_t *count, void *stream);
 
 /* Convenience: encode host filters into a pinned staging buffer, copy them
- * to the device (stream-ordered allocation on `stream`) and run
- * jag_search_encoded; asynchronous on `stream` (the call does not wait for
- * the stream; a staging buffer is refilled only once its copy has run). */
+ * to the device and run jag_search_encoded; asynchronous on `stream` (the
+ * call does not wait for the stream; a staging buffer is refilled only once
+ * its copy has run).  The copy (into stream-ordered memory) runs on a
+ * stream the index owns, so it overlaps work already queued on `stream`;
+ * `stream` waits for it, by an event, only where the search begins. */
 jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t nq, const jag_filter *F,
                             const int32_t *pool, int64_t pool_len, int32_t k,
                             const jag_search_params *S, int32_t *ids, float *dists,

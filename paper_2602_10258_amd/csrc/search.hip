@@ -28,6 +28,9 @@ struct StagingBuf {
 struct StagingRing {
     std::mutex mu;
     std::vector<StagingBuf> bufs;
+    // the uploads run on a stream of their own, so that a call's copy does
+    // not wait behind the caller's earlier work (created on first use)
+    hipStream_t copy = nullptr;
 };
 
 namespace {
@@ -919,6 +922,10 @@ constexpr size_t kStagingMax = 8;  // buffers per index; beyond that a caller wa
 void free_staging(StagingRing *r)
 {
     if (!r) return;
+    if (r->copy) {
+        (void)hipStreamSynchronize(r->copy);
+        (void)hipStreamDestroy(r->copy);
+    }
     for (auto &b : r->bufs) {
         if (b.copied) {
             (void)hipEventSynchronize(b.copied);
@@ -1018,20 +1025,32 @@ extern "C" jag_status jag_search_batch(jag_index *idx, const float *Q, int64_t n
         jag::staging_release(ix.staging, slot);
         return st;
     }
-    void *drec = nullptr;
+    // The records go up on the ring's copy stream: the copy of one call then
+    // overlaps the searches still running on the caller's stream, which
+    // waits for the copy only where its search begins.
     hipStream_t s = (hipStream_t)stream;
-    if (hipMallocAsync(&drec, (size_t)bytes, s) != hipSuccess) {
+    {
+        std::lock_guard<std::mutex> g(ix.staging->mu);
+        if (!ix.staging->copy && hipStreamCreateWithFlags(&ix.staging->copy, hipStreamNonBlocking) != hipSuccess) {
+            ix.staging->copy = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    hipStream_t cs = ix.staging->copy ? ix.staging->copy : s;
+    void *drec = nullptr;
+    if (hipMallocAsync(&drec, (size_t)bytes, cs) != hipSuccess) {
         (void)hipGetLastError();
         jag::staging_release(ix.staging, slot);
         jag::set_error("device allocation for filter records failed");
         return JAG_ENOMEM;
     }
-    hipError_t e = hipMemcpyAsync(drec, buf.host, (size_t)bytes, hipMemcpyHostToDevice, s);
-    // the buffer may be filled again once this copy has run
-    hipError_t er = hipEventRecord(buf.copied, s);
+    hipError_t e = hipMemcpyAsync(drec, buf.host, (size_t)bytes, hipMemcpyHostToDevice, cs);
+    // the buffer may be filled again, and the search may start, once this copy has run
+    hipError_t er = hipEventRecord(buf.copied, cs);
+    if (e == hipSuccess && er == hipSuccess && cs != s) er = hipStreamWaitEvent(s, buf.copied, 0);
     jag::staging_release(ix.staging, slot);
     if (e != hipSuccess || er != hipSuccess) {
-        (void)hipFreeAsync(drec, s);
+        (void)hipFreeAsync(drec, cs);
         jag::set_error("filter upload failed: %s", hipGetErrorString(e != hipSuccess ? e : er));
         return JAG_EDEVICE;
     }
