@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libjag.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HOST_SRC = ["api.cpp", "builder.cpp"]
-DEV_SRC = ["search.hip", "serve_kernels.hip", "predictor.hip", "serve.hip", "build.hip", "probe.hip"]
+DEV_SRC = ["search.hip", "serve_kernels.hip", "predictor.hip", "serve.hip", "build.hip", "probe.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3", "-fopenmp-simd", "-Wall",

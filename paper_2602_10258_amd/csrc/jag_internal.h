@@ -54,8 +54,9 @@ struct Predictor {
 };
 
 // Pinned host buffers that jag_search_batch stages encoded filters in
-// (search.hip); each is reused once the copy out of it has completed.
+// (batch.hip); each is reused once the copy out of it has completed.
 struct StagingRing;
+StagingRing *new_staging();
 void free_staging(StagingRing *r);
 
 struct Index {

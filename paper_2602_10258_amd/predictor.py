@@ -5,7 +5,9 @@ Pipeline, all on the GPU through the C ABI:
   2. one traced search per ladder width L (learned == 2): the predictor
      features after four expansions, and the answer at L;
   3. target of a query = the smallest ladder index whose answer reaches
-     recall@k >= 0.95 (for k = 10 that is every exact neighbour found);
+     recall@k >= 0.95 (for k = 10 that is every exact neighbour found); a
+     query that reaches it nowhere on the ladder gets the smallest index at
+     which its recall peaks;
   4. minibatch Adam on the GPU (jag_train_predictor), then jag_set_predictor
      with a hop cap rho = the 99th percentile of expansions / L at the target.
 """
@@ -86,6 +88,12 @@ def exact_answers(idx, Qd, rec, k: int):
 
 
 def targets_from(all_ids, exact_ids, exact_cnt, k: int, need: float = 0.95):
+    """Per query, the smallest ladder index whose search reaches recall@k >=
+    need.  A query that reaches it at no beam of the ladder gets the smallest
+    index at which its recall is highest over the ladder: a wider beam finds
+    it nothing more, so training it toward the widest beam would only teach
+    the network to spend work that buys no recall.  Returns (targets,
+    reached)."""
     nl, nq, _ = all_ids.shape
     tgt = np.full(nq, nl - 1, dtype=np.int32)
     reached = np.zeros(nq, dtype=bool)
@@ -96,12 +104,13 @@ def targets_from(all_ids, exact_ids, exact_cnt, k: int, need: float = 0.95):
             reached[q] = True
             continue
         gt = set(exact_ids[q, :den].tolist())
-        for i in range(nl):
-            hits = len(gt.intersection(all_ids[i, q].tolist()))
-            if hits / den >= need:
-                tgt[q] = i
-                reached[q] = True
-                break
+        hits = [len(gt.intersection(all_ids[i, q].tolist())) for i in range(nl)]
+        ok = [i for i in range(nl) if hits[i] / den >= need]
+        if ok:
+            tgt[q] = ok[0]
+            reached[q] = True
+        else:
+            tgt[q] = hits.index(max(hits))
     return tgt, reached
 
 

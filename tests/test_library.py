@@ -215,3 +215,23 @@ def test_gather_ceiling_rejects_bad_arguments():
         st = L.jag_gather_ceiling(args[0], *args[1:], None, C.byref(out))
         assert st == jag.JAG_EINVAL, args
     assert out.value == -1.0
+
+
+def test_predictor_targets_take_the_recall_plateau_of_unreachable_queries():
+    """Target = smallest ladder index reaching recall 0.95; a query that never
+    reaches it gets the smallest index where its recall peaks (not the widest
+    beam), and queries without valid items get index 0."""
+    from paper_2602_10258_amd.predictor import targets_from
+    ex = np.array([[1, 2], [3, 4], [5, 6], [7, 8]], np.int32)
+    cnt = np.array([2, 2, 2, 0])
+    ids = np.array([[[1, 9], [3, 9], [5, 9], [0, 0]],
+                    [[1, 2], [3, 9], [9, 9], [0, 0]],
+                    [[1, 2], [3, 4], [5, 6], [0, 0]],
+                    [[1, 2], [3, 9], [5, 6], [0, 0]]], np.int32)  # 4 levels x 4 queries x k
+    t, r = targets_from(ids, ex, cnt, 2)
+    assert t.tolist() == [1, 2, 2, 0] and r.tolist() == [True, True, True, True]
+    ids2 = ids.copy()
+    ids2[:, 1, 1] = 9   # query 1 never finds label 4: peak (1 hit) first at level 0
+    ids2[:, 2, :] = [[5, 9], [9, 9], [5, 9], [5, 9]]  # query 2 peaks at 1 hit, first at level 0
+    t, r = targets_from(ids2, ex, cnt, 2)
+    assert t.tolist() == [1, 0, 0, 0] and r.tolist() == [True, False, False, True]
