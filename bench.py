@@ -696,7 +696,10 @@ class Leg:
 
     def learned_sweep(self, ntrain, L95, ladder_top=None, dump=None):
         """Fit the predictor on a separate query set of this filter type and
-        sweep its offset; the narrowest ladder whose sweep reaches 0.95."""
+        sweep its offset; the narrowest ladder whose sweep reaches 0.95.  Both
+        target rules for training queries that never reach 0.95 (the widest
+        beam, or the beam where their recall peaks) are fitted and swept; the
+        one with the higher QPS at 0.95 stays attached to the index."""
         from paper_2602_10258_amd import jag
         from paper_2602_10258_amd import predictor as pred
         from workloads.gen import extra_queries
@@ -706,38 +709,54 @@ class Leg:
                                    qseed=1000)
         keep = Ft[:, 0] == self.ftype
         Qt, Ft = np.ascontiguousarray(Qt[keep][:ntrain]), np.ascontiguousarray(Ft[keep][:ntrain])
-        learned, lad, rep = [], None, None
-        for top in ladder_tops(L95, ladder_top):
-            lad = learned_ladder(L95, top)
-            log(f"{self.tag()} learned ladder {lad.tolist()}")
-            P, rho, rep = pred.fit(cfg.ix16, Qt, Ft, pt, k=self.k, exact_idx=cfg.ix32, rerank_mult=4, dump=dump,
-                                   ladder=lad)
-            log(f"{self.tag()} predictor fitted on {rep.n_train} traces in {time.time() - t3:.1f}s: loss "
-                f"{rep.loss_first:.3f} -> {rep.loss_last:.3f}, rho={rho:.2f}, unreachable={rep.unreachable}")
-            learned = []
-            for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 6.0]:
-                r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=delta, rerank_mult=4))
-                r["delta"] = delta
-                learned.append(r)
-                log(f"{self.tag()} learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} qps={r['qps']:.0f} "
-                    f"mean Lhat={r['lhat']:.1f}")
-                if r["recall"] >= 0.995 or (r["recall"] >= 0.95 and delta >= 1.0):
+
+        def sweep(rule):
+            learned, lad, rep, P, rho = [], None, None, None, None
+            for top in ladder_tops(L95, ladder_top):
+                lad = learned_ladder(L95, top)
+                log(f"{self.tag()} learned ladder {lad.tolist()}, unreachable targets: {rule}")
+                P, rho, rep = pred.fit(cfg.ix16, Qt, Ft, pt, k=self.k, exact_idx=cfg.ix32, rerank_mult=4,
+                                       dump=dump, ladder=lad, unreachable=rule)
+                log(f"{self.tag()} predictor fitted on {rep.n_train} traces in {time.time() - t3:.1f}s: loss "
+                    f"{rep.loss_first:.3f} -> {rep.loss_last:.3f}, rho={rho:.2f}, unreachable={rep.unreachable}")
+                learned = []
+                for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 6.0]:
+                    r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=delta, rerank_mult=4))
+                    r["delta"] = delta
+                    learned.append(r)
+                    log(f"{self.tag()} learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} "
+                        f"qps={r['qps']:.0f} mean Lhat={r['lhat']:.1f}")
+                    if r["recall"] >= 0.995 or (r["recall"] >= 0.95 and delta >= 1.0):
+                        break
+                if any(r["recall"] >= 0.95 for r in learned):
                     break
-            if any(r["recall"] >= 0.95 for r in learned):
-                break
-        # bisect the offset between the last point below 0.95 and the first at
-        # or above it (four halvings; midpoints rounded to 4 decimals)
-        j = next((i for i, r in enumerate(learned) if r["recall"] >= 0.95), None)
-        if j:
-            lo, hi = learned[j - 1]["delta"], learned[j]["delta"]
-            for _ in range(4):
-                mid = round((lo + hi) / 2, 4)
-                r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=mid, rerank_mult=4))
-                r["delta"] = mid
-                learned.append(r)
-                log(f"{self.tag()}   refine delta={mid:+.4f} recall={r['recall']:.4f} qps={r['qps']:.0f}")
-                lo, hi = (lo, mid) if r["recall"] >= 0.95 else (mid, hi)
-            learned.sort(key=lambda r: r["delta"])
+            # bisect the offset between the last point below 0.95 and the first
+            # at or above it (four halvings; midpoints rounded to 4 decimals)
+            j = next((i for i, r in enumerate(learned) if r["recall"] >= 0.95), None)
+            if j:
+                lo, hi = learned[j - 1]["delta"], learned[j]["delta"]
+                for _ in range(4):
+                    mid = round((lo + hi) / 2, 4)
+                    r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=mid, rerank_mult=4))
+                    r["delta"] = mid
+                    learned.append(r)
+                    log(f"{self.tag()}   refine delta={mid:+.4f} recall={r['recall']:.4f} qps={r['qps']:.0f}")
+                    lo, hi = (lo, mid) if r["recall"] >= 0.95 else (mid, hi)
+                learned.sort(key=lambda r: r["delta"])
+            return learned, lad, rep, P, rho
+
+        runs = {rule: sweep(rule) for rule in ("widest", "plateau")}
+
+        def score(run):
+            best = at95(run[0])[0]
+            return best["qps"] if best else -1.0
+        rule = max(runs, key=lambda r: score(runs[r]))
+        learned, lad, rep, P, rho = runs[rule]
+        if P is not None:
+            jag.jag_set_predictor(cfg.ix16, P, np.maximum(lad, self.k), rho)
+        self.target_rules = {r: round(score(v), 1) if score(v) > 0 else None for r, v in runs.items()}
+        self.target_rule = rule
+        log(f"{self.tag()} QPS at 0.95 by target rule: {self.target_rules}; keeping {rule}")
         return learned, lad, rep
 
     def tag(self):
@@ -878,6 +897,8 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
                "learned_bf16_rerank_interp": interp_l and round(interp_l, 1),
                "learned_delta": best_l and best_l["delta"], "learned_mean_beam": best_l and round(best_l["lhat"], 2)},
            "learned_schedules": schedules,
+           "learned_target_rule": getattr(leg, "target_rule", None),
+           "learned_qps_by_target_rule": getattr(leg, "target_rules", None),
            "learned_over_fp32_fixed": (best_l and best_f and round(best_l["qps"] / best_f["qps"], 4)) or None,
            "learned_over_bf16_fixed": (best_l and best_16 and round(best_l["qps"] / best_16["qps"], 4)) or None,
            "learned_ladder": None if lad is None else lad.tolist(),

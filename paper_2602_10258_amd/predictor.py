@@ -6,8 +6,8 @@ Pipeline, all on the GPU through the C ABI:
      features after four expansions, and the answer at L;
   3. target of a query = the smallest ladder index whose answer reaches
      recall@k >= 0.95 (for k = 10 that is every exact neighbour found); a
-     query that reaches it nowhere on the ladder gets the smallest index at
-     which its recall peaks;
+     query that reaches it nowhere on the ladder gets the widest index, or
+     the smallest index at which its recall peaks;
   4. minibatch Adam on the GPU (jag_train_predictor), then jag_set_predictor
      with a hop cap rho = the 99th percentile of expansions / L at the target.
 """
@@ -87,13 +87,15 @@ def exact_answers(idx, Qd, rec, k: int):
     return ids.cpu().numpy(), cnt.cpu().numpy()
 
 
-def targets_from(all_ids, exact_ids, exact_cnt, k: int, need: float = 0.95):
+def targets_from(all_ids, exact_ids, exact_cnt, k: int, need: float = 0.95, unreachable: str = "widest"):
     """Per query, the smallest ladder index whose search reaches recall@k >=
-    need.  A query that reaches it at no beam of the ladder gets the smallest
-    index at which its recall is highest over the ladder: a wider beam finds
-    it nothing more, so training it toward the widest beam would only teach
-    the network to spend work that buys no recall.  Returns (targets,
-    reached)."""
+    need.  A query that reaches it at no beam of the ladder gets the widest
+    index (unreachable="widest"), or the smallest index at which its recall
+    is highest over the ladder ("plateau": a wider beam finds it nothing
+    more).  Which serves a workload better is measured: on the range
+    workload the plateau rule saves work, on label-set workloads, whose
+    recall keeps creeping up with the beam, the widest target does better.
+    Returns (targets, reached)."""
     nl, nq, _ = all_ids.shape
     tgt = np.full(nq, nl - 1, dtype=np.int32)
     reached = np.zeros(nq, dtype=bool)
@@ -109,24 +111,26 @@ def targets_from(all_ids, exact_ids, exact_cnt, k: int, need: float = 0.95):
         if ok:
             tgt[q] = ok[0]
             reached[q] = True
-        else:
+        elif unreachable == "plateau":
             tgt[q] = hits.index(max(hits))
     return tgt, reached
 
 
 def fit(idx, Q, F, pool, k: int = 10, epochs: int = 40, batch: int = 512, lr: float = 3e-3,
         seed: int = 0, ladder=LADDER, exact_idx=None, rerank_mult: int = 0,
-        dump: str | None = None) -> tuple[np.ndarray, float, FitReport]:
+        dump: str | None = None, unreachable: str = "widest") -> tuple[np.ndarray, float, FitReport]:
     """Train on (Q, F) and attach the predictor to ``idx``.  ``exact_idx`` is an
     index over the same data holding an FP32 copy (defaults to ``idx``);
-    ``rerank_mult`` must match the setting the learned search will use."""
+    ``rerank_mult`` must match the setting the learned search will use;
+    ``unreachable`` is the target rule of queries that never reach recall 0.95
+    (``targets_from``)."""
     import torch
     Qd, rec = _device_batch(idx, Q, F, pool)
     ex = exact_idx if exact_idx is not None else idx
     Qe, rece = (Qd, rec) if ex is idx else _device_batch(ex, Q, F, pool)
     exact_ids, exact_cnt = exact_answers(ex, Qe, rece, k)
     feats, all_ids, hops = traces(idx, Qd, rec, k, ladder, rerank_mult)
-    tgt, reached = targets_from(all_ids, exact_ids, exact_cnt, k)
+    tgt, reached = targets_from(all_ids, exact_ids, exact_cnt, k, unreachable=unreachable)
     if dump:
         nl, nq = all_ids.shape[0], all_ids.shape[1]
         hits = np.zeros((nl, nq), dtype=np.int8)

@@ -219,8 +219,8 @@ def test_gather_ceiling_rejects_bad_arguments():
 
 def test_predictor_targets_take_the_recall_plateau_of_unreachable_queries():
     """Target = smallest ladder index reaching recall 0.95; a query that never
-    reaches it gets the smallest index where its recall peaks (not the widest
-    beam), and queries without valid items get index 0."""
+    reaches it gets the widest index, or with the plateau rule the smallest
+    index where its recall peaks; queries without valid items get index 0."""
     from paper_2602_10258_amd.predictor import targets_from
     ex = np.array([[1, 2], [3, 4], [5, 6], [7, 8]], np.int32)
     cnt = np.array([2, 2, 2, 0])
@@ -233,5 +233,7 @@ def test_predictor_targets_take_the_recall_plateau_of_unreachable_queries():
     ids2 = ids.copy()
     ids2[:, 1, 1] = 9   # query 1 never finds label 4: peak (1 hit) first at level 0
     ids2[:, 2, :] = [[5, 9], [9, 9], [5, 9], [5, 9]]  # query 2 peaks at 1 hit, first at level 0
-    t, r = targets_from(ids2, ex, cnt, 2)
+    t, r = targets_from(ids2, ex, cnt, 2, unreachable="plateau")
     assert t.tolist() == [1, 0, 0, 0] and r.tolist() == [True, False, False, True]
+    t, r = targets_from(ids2, ex, cnt, 2)  # default: unreachable queries train toward the widest beam
+    assert t.tolist() == [1, 3, 3, 0] and r.tolist() == [True, False, False, True]
