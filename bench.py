@@ -92,6 +92,9 @@ def parse():
                     help="profile mode, learned: the one-pass schedule (prediction inside the search)")
     ap.add_argument("--ladder", default=None,
                     help="profile mode, learned: comma-separated ladder (as the bench line reports it)")
+    ap.add_argument("--target-rule", default="widest", choices=["widest", "plateau"],
+                    help="profile mode, learned: training target of queries that never reach recall 0.95 "
+                         "(as the bench line reports it)")
     ap.add_argument("--ladder-top", type=int, default=None,
                     help="widest beam of the learned ladder (default: 1.4x the fixed beam at recall 0.95)")
     ap.add_argument("--dump-traces", default=None, help="save predictor traces to this .npz")
@@ -1035,7 +1038,7 @@ def profile_main(args, dev):
             Qt, Ft = np.ascontiguousarray(Qt[keep][:args.ntrain]), np.ascontiguousarray(Ft[keep][:args.ntrain])
         lad = (np.array([int(x) for x in args.ladder.split(",")], dtype=np.int32) if args.ladder
                else learned_ladder(None))
-        pred.fit(ix, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4, ladder=lad)
+        pred.fit(ix, Qt, Ft, pt, k=k, exact_idx=ix32, rerank_mult=4, ladder=lad, unreachable=args.target_rule)
         sp = jag.SearchParams(L=k, learned=1, delta=args.delta, rerank_mult=4,
                               single_pass=1 if args.single_pass else 0)
     else:
