@@ -312,21 +312,64 @@ __device__ __forceinline__ void eval_rows(const unsigned char *base, int stride,
     }
 }
 
-// Generic FP32 row distance with a runtime chunk count (for reranking).
-__device__ __forceinline__ float row_dist_f32_rt(const unsigned char *row, const float *q, int d,
-                                                 int nch, int sub)
+// FP32 squared distance of one row of the rerank copy, in the lane layout of
+// the search store: lane `sub` of a G-lane group takes the elements of chunks
+// j*G + sub (EPC each), so the query registers serve both passes.  Groups of
+// four floats that start at or beyond d are not read (they add nothing); all
+// loads of the row are issued before the first use.
+template <int STORE, int G, int CH>
+__device__ __forceinline__ float row_dist_f32(const unsigned char *row, const QueryRegs<STORE, G, CH> &q,
+                                              int d, int sub)
 {
-    float acc = 0.f;
-    for (int j = 0; j < nch; j++) {
-        int e0 = (j * 4 + sub) * 4;
-        float4 x = *reinterpret_cast<const float4 *>(row + (j * 4 + sub) * 16);
-        float xs[4] = {x.x, x.y, x.z, x.w};
+    constexpr int EPC = StoreTraits<STORE>::EPC;
+    constexpr int NV = EPC / 4;
+    // elements this lane may read: chunk offsets below lim (kept opaque so
+    // that the compiler does not keep the query loader's indices alive, in
+    // spilled registers, until the rerank)
+    int lim = d - sub * EPC;
+    asm volatile("" : "+v"(lim));
+    row += 4 * sub * EPC;
+    float4 x[CH][NV];
 #pragma unroll
-        for (int e = 0; e < 4; e++) acc = acc_sq(acc, e0 + e < d ? q[e0 + e] : 0.f, xs[e]);
-    }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
+    for (int j = 0; j < CH; j++)
+#pragma unroll
+        for (int t = 0; t < NV; t++) {
+            const int o = j * G * EPC + 4 * t;
+            x[j][t] = o < lim ? *reinterpret_cast<const float4 *>(row + 4 * o) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < CH; j++)
+#pragma unroll
+        for (int t = 0; t < NV; t++) {
+            acc = acc_sq(acc, q.v[j][4 * t + 0], x[j][t].x);
+            acc = acc_sq(acc, q.v[j][4 * t + 1], x[j][t].y);
+            acc = acc_sq(acc, q.v[j][4 * t + 2], x[j][t].z);
+            acc = acc_sq(acc, q.v[j][4 * t + 3], x[j][t].w);
+        }
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) acc += __shfl_xor(acc, m, 64);
     return acc;
+}
+
+// FP32 distances of the m entries cid[0..m) into cd2[], two rows per lane
+// group in flight (as eval_rows).
+template <int STORE, int G, int CH>
+__device__ __forceinline__ void rerank_rows(const unsigned char *base, int stride, const int32_t *cid,
+                                            float *cd2, int m, const QueryRegs<STORE, G, CH> &q, int d)
+{
+    const int lane = threadIdx.x;
+    const int sub = lane & (G - 1), grp = lane / G;
+    constexpr int P = 64 / G;
+    for (int r = 0; r < m; r += 2 * P) {
+        int c0 = r + grp, c1 = r + P + grp;
+        int i0 = cid[c0 < m ? c0 : 0], i1 = cid[c1 < m ? c1 : 0];
+        float d0 = row_dist_f32<STORE, G, CH>(base + (int64_t)i0 * stride, q, d, sub);
+        float d1 = 0.f;
+        if (r + P < m) d1 = row_dist_f32<STORE, G, CH>(base + (int64_t)i1 * stride, q, d, sub);
+        if (sub == 0 && c0 < m) cd2[c0] = d0;
+        if (sub == 0 && c1 < m) cd2[c1] = d1;
+    }
 }
 
 // ---------------------------------------------------------------- LDS list
@@ -842,14 +885,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             s.cdf[lane] = (uint32_t)(s.key[lane] >> 32);
         }
         __syncthreads();
-        const int sub = lane & 3, grp = lane >> 2;
-        const int nch = a.f32_stride >> 6;
-        for (int r = 0; r < rk; r += 16) {
-            int c = r + grp;
-            int id = s.cid[c < rk ? c : 0];
-            float dd = row_dist_f32_rt(a.f32 + (int64_t)id * a.f32_stride, qv, a.d, nch, sub);
-            if (sub == 0 && c < rk) s.cd2[c] = dd;
-        }
+        rerank_rows<STORE, G, CH>(a.f32, a.f32_stride, s.cid, s.cd2, rk, qr, a.d);
         __syncthreads();
         uint64_t ck = 0;
         uint32_t ci = 0;

@@ -43,13 +43,12 @@ def row_terms(store: int, d: int) -> tuple[int, int]:
 def lane_order(store: int, d: int) -> list[int]:
     """The oracle's contract-mode order for the GPU's row layout: (G lanes,
     elements per 16-byte chunk, chunks per lane) of the search store, then
-    of the FP32 rows the rerank reads (four lanes over 64-byte-padded rows,
-    or the store's own rows for an FP32 store)."""
+    of the FP32 rows the rerank reads, which the GPU splits over lanes as
+    it splits the store's rows (the same triple)."""
     eb = {0: 4, 1: 2, 2: 1}[store]
     stride, G = _layout(eb * d + (4 if store == 2 else 0))
     out = [G, 16 // eb, stride // (16 * G)]
-    f32_stride = stride if store == 0 else _layout(4 * d)[0]
-    return out + [4, 4, f32_stride // 64]
+    return out + out
 
 
 def compare_strict(gpu_ids, gpu_d2, gpu_cnt, orc, what=""):
@@ -62,10 +61,13 @@ def compare_strict(gpu_ids, gpu_d2, gpu_cnt, orc, what=""):
 
 
 def tau_for(store: int, d: int, rerank_d: int | None = None) -> float:
+    """tau for a search over `store` rows of d elements; with rerank_d, also
+    for the FP32 rescoring, whose rows the GPU splits over lanes as it
+    splits the store's (the same m and G per row)."""
     m, G = row_terms(store, d)
     eps = (m + 2 + math.log2(G)) * U
     if rerank_d is not None:
-        m2, G2 = row_terms(0, rerank_d)
+        m2, G2 = row_terms(store, rerank_d)
         eps = max(eps, (m2 + 2 + math.log2(G2)) * U)
     tau = 2.02 * eps
     assert tau < 1e-5
