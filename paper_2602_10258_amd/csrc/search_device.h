@@ -147,12 +147,14 @@ template <int AK>
 __device__ __forceinline__ void load_row_attr(ItemAttr &at, const FilterRecord &f, const int32_t *row,
                                               int j, const SearchArgs &a)
 {
+    // 32-bit byte offsets from the row (the same in every lane): the loads
+    // take the row's address from scalar registers
+    const unsigned char *rb = reinterpret_cast<const unsigned char *>(row);
     if (AK == AK_SCALAR || (AK == AK_ANY && f.type == F_RANGE)) {
-        at.scalar = row[a.scal_word_off + j];
+        at.scalar = *reinterpret_cast<const int32_t *>(rb + (uint32_t)(4 * (a.scal_word_off + j)));
         return;
     }
-    load_label_words(at.w, reinterpret_cast<const unsigned char *>(row + a.lab_word_off) + j * a.W * 2,
-                     a.W >> 1);
+    load_label_words(at.w, rb + (uint32_t)(4 * a.lab_word_off + j * a.W * 2), a.W >> 1);
 }
 
 template <int AK>
@@ -239,16 +241,20 @@ __device__ __forceinline__ float acc_sq(float acc, float qv, float x)
     return __builtin_fmaf(t, t, acc);
 }
 
-// Partial squared distance of one row held by a G-lane group; the partial
-// sums of the group are then added in a fixed butterfly order.
-template <int STORE, int G, int CH>
-__device__ __forceinline__ float row_dist(const unsigned char *row, const QueryRegs<STORE, G, CH> &q,
-                                          int sub)
+// Lane `sub` of a G-lane group loads its chunks j*G + sub of a row.
+template <int G, int CH>
+__device__ __forceinline__ void row_load(uint4 (&c)[CH], const unsigned char *row, int sub)
 {
-    uint4 c[CH];
 #pragma unroll
     for (int j = 0; j < CH; j++)
         c[j] = *reinterpret_cast<const uint4 *>(row + (j * G + sub) * 16);
+}
+
+// Partial squared distance of the chunks a lane loaded; the partial sums of
+// the group are then added in a fixed butterfly order.
+template <int STORE, int G, int CH>
+__device__ __forceinline__ float row_sum(const uint4 (&c)[CH], const QueryRegs<STORE, G, CH> &q, int sub)
+{
     float acc = 0.f;
     if constexpr (STORE == JAG_STORE_F32) {
 #pragma unroll
@@ -292,8 +298,23 @@ __device__ __forceinline__ float row_dist(const unsigned char *row, const QueryR
     return acc;
 }
 
-// Squared distances of the m candidates cid[0..m) into cd2[], G lanes per row.
-template <int STORE, int G, int CH>
+// Whether a search kernel keeps two rows per lane group in flight (PAIR
+// below): where the query registers and two rows' chunks fit in half of the
+// 96-register budget, and the label words of the filter step or the FP8
+// decoding do not crowd them out (elsewhere pairs measured as many more
+// spills in the expansion loop than they save in round trips).
+template <int STORE, int CH, int AK>
+constexpr bool pair_rows()
+{
+    return CH * StoreTraits<STORE>::EPC + 8 * CH <= 48 && STORE != JAG_STORE_FP8_E4M3 &&
+           (AK == AK_SCALAR || STORE == JAG_STORE_F32);
+}
+
+// Squared distances of the m candidates cid[0..m) into cd2[], G lanes per
+// row, 64/G rows per group of lanes at a time.  With PAIR, when two rows per
+// lane group remain both rows' loads are issued before either sum, so the
+// pair costs one round trip to memory.
+template <int STORE, int G, int CH, bool PAIR = false>
 __device__ __forceinline__ void eval_rows(const unsigned char *base, int stride, const int32_t *cid,
                                           float *cd2, int m, const QueryRegs<STORE, G, CH> &q)
 {
@@ -304,32 +325,41 @@ __device__ __forceinline__ void eval_rows(const unsigned char *base, int stride,
         int c0 = r + grp, c1 = r + P + grp;
         // rows past m re-read row cid[0] so every lane stays in bounds
         int i0 = cid[c0 < m ? c0 : 0], i1 = cid[c1 < m ? c1 : 0];
-        float d0 = row_dist<STORE, G, CH>(base + (int64_t)i0 * stride, q, sub);
-        float d1 = 0.f;
-        if (r + P < m) d1 = row_dist<STORE, G, CH>(base + (int64_t)i1 * stride, q, sub);
+        uint4 x0[CH];
+        row_load<G, CH>(x0, base + (int64_t)i0 * stride, sub);
+        float d0, d1 = 0.f;
+        if (PAIR && r + P < m) {
+            uint4 x1[CH];
+            row_load<G, CH>(x1, base + (int64_t)i1 * stride, sub);
+            d0 = row_sum<STORE, G, CH>(x0, q, sub);
+            d1 = row_sum<STORE, G, CH>(x1, q, sub);
+        } else {
+            d0 = row_sum<STORE, G, CH>(x0, q, sub);
+            if (r + P < m) {
+                uint4 x1[CH];
+                row_load<G, CH>(x1, base + (int64_t)i1 * stride, sub);
+                d1 = row_sum<STORE, G, CH>(x1, q, sub);
+            }
+        }
         if (sub == 0 && c0 < m) cd2[c0] = d0;
         if (sub == 0 && c1 < m) cd2[c1] = d1;
     }
 }
 
-// FP32 squared distance of one row of the rerank copy, in the lane layout of
-// the search store: lane `sub` of a G-lane group takes the elements of chunks
-// j*G + sub (EPC each), so the query registers serve both passes.  Groups of
-// four floats that start at or beyond d are not read (they add nothing); all
-// loads of the row are issued before the first use.
+// One row of the FP32 rerank copy, in the lane layout of the search store:
+// lane `sub` of a G-lane group loads the elements of chunks j*G + sub (EPC
+// each), so the query registers serve both passes; row_sum_f32 then adds the
+// lane's squared differences and the group's partial sums (butterfly).
+// Groups of four floats that start at or beyond d (offsets from the lane's
+// first element at or beyond lim = d - sub*EPC) are not read: they add
+// nothing.
 template <int STORE, int G, int CH>
-__device__ __forceinline__ float row_dist_f32(const unsigned char *row, const QueryRegs<STORE, G, CH> &q,
-                                              int d, int sub)
+__device__ __forceinline__ void row_load_f32(float4 (&x)[CH][StoreTraits<STORE>::EPC / 4],
+                                             const unsigned char *row, int lim, int sub)
 {
     constexpr int EPC = StoreTraits<STORE>::EPC;
     constexpr int NV = EPC / 4;
-    // elements this lane may read: chunk offsets below lim (kept opaque so
-    // that the compiler does not keep the query loader's indices alive, in
-    // spilled registers, until the rerank)
-    int lim = d - sub * EPC;
-    asm volatile("" : "+v"(lim));
     row += 4 * sub * EPC;
-    float4 x[CH][NV];
 #pragma unroll
     for (int j = 0; j < CH; j++)
 #pragma unroll
@@ -337,6 +367,13 @@ __device__ __forceinline__ float row_dist_f32(const unsigned char *row, const Qu
             const int o = j * G * EPC + 4 * t;
             x[j][t] = o < lim ? *reinterpret_cast<const float4 *>(row + 4 * o) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
+}
+
+template <int STORE, int G, int CH>
+__device__ __forceinline__ float row_sum_f32(const float4 (&x)[CH][StoreTraits<STORE>::EPC / 4],
+                                             const QueryRegs<STORE, G, CH> &q)
+{
+    constexpr int NV = StoreTraits<STORE>::EPC / 4;
     float acc = 0.f;
 #pragma unroll
     for (int j = 0; j < CH; j++)
@@ -352,21 +389,71 @@ __device__ __forceinline__ float row_dist_f32(const unsigned char *row, const Qu
     return acc;
 }
 
-// FP32 distances of the m entries cid[0..m) into cd2[], two rows per lane
-// group in flight (as eval_rows).
-template <int STORE, int G, int CH>
-__device__ __forceinline__ void rerank_rows(const unsigned char *base, int stride, const int32_t *cid,
-                                            float *cd2, int m, const QueryRegs<STORE, G, CH> &q, int d)
+// Rows whose lane share in the store's layout is wide (more than 32 floats
+// per lane, where the query registers are mostly spilled already) are
+// rescored in a layout of their own: 4 lanes per row over the 64-byte
+// chunks of the FP32 row (lane sub takes the 16-byte pieces 4j + sub), the
+// query's values read from its vector, one piece at a time.
+__device__ __forceinline__ float row_dist_f32_rt(const unsigned char *row, const float *q, int d,
+                                                 int nch, int sub)
 {
+    float acc = 0.f;
+    for (int j = 0; j < nch; j++) {
+        int e0 = (j * 4 + sub) * 4;
+        float4 x = *reinterpret_cast<const float4 *>(row + (j * 4 + sub) * 16);
+        float xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc = acc_sq(acc, e0 + e < d ? q[e0 + e] : 0.f, xs[e]);
+    }
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    return acc;
+}
+
+// FP32 distances of the m entries cid[0..m) into cd2[] (PAIR as in
+// eval_rows).
+template <int STORE, int G, int CH, bool PAIR = false>
+__device__ __forceinline__ void rerank_rows(const unsigned char *base, int stride, const int32_t *cid,
+                                            float *cd2, int m, const QueryRegs<STORE, G, CH> &q,
+                                            const float *qv, int d)
+{
+    constexpr int NV = StoreTraits<STORE>::EPC / 4;
     const int lane = threadIdx.x;
     const int sub = lane & (G - 1), grp = lane / G;
     constexpr int P = 64 / G;
+    // elements this lane may read: chunk offsets below lim (kept opaque so
+    // that the compiler does not keep the query loader's indices alive, in
+    // spilled registers, until the rerank)
+    if constexpr (CH * StoreTraits<STORE>::EPC > 32) {
+        const int sub4 = lane & 3, grp4 = lane >> 2, nch = stride >> 6;
+        for (int r = 0; r < m; r += 16) {
+            const int c = r + grp4;
+            const float dd = row_dist_f32_rt(base + (int64_t)cid[c < m ? c : 0] * stride, qv, d, nch, sub4);
+            if (sub4 == 0 && c < m) cd2[c] = dd;
+        }
+        return;
+    }
+    int lim = d - sub * StoreTraits<STORE>::EPC;
+    asm volatile("" : "+v"(lim));
     for (int r = 0; r < m; r += 2 * P) {
         int c0 = r + grp, c1 = r + P + grp;
         int i0 = cid[c0 < m ? c0 : 0], i1 = cid[c1 < m ? c1 : 0];
-        float d0 = row_dist_f32<STORE, G, CH>(base + (int64_t)i0 * stride, q, d, sub);
-        float d1 = 0.f;
-        if (r + P < m) d1 = row_dist_f32<STORE, G, CH>(base + (int64_t)i1 * stride, q, d, sub);
+        float4 x0[CH][NV];
+        row_load_f32<STORE, G, CH>(x0, base + (int64_t)i0 * stride, lim, sub);
+        float d0, d1 = 0.f;
+        if (PAIR && r + P < m) {
+            float4 x1[CH][NV];
+            row_load_f32<STORE, G, CH>(x1, base + (int64_t)i1 * stride, lim, sub);
+            d0 = row_sum_f32<STORE, G, CH>(x0, q);
+            d1 = row_sum_f32<STORE, G, CH>(x1, q);
+        } else {
+            d0 = row_sum_f32<STORE, G, CH>(x0, q);
+            if (r + P < m) {
+                float4 x1[CH][NV];
+                row_load_f32<STORE, G, CH>(x1, base + (int64_t)i1 * stride, lim, sub);
+                d1 = row_sum_f32<STORE, G, CH>(x1, q);
+            }
+        }
         if (sub == 0 && c0 < m) cd2[c0] = d0;
         if (sub == 0 && c1 < m) cd2[c1] = d1;
     }
@@ -669,7 +756,12 @@ __device__ __forceinline__ float bf16f(uint16_t h) { return __uint_as_float((uin
 // Lane j computes hidden unit j; the output is a butterfly sum over lanes.
 __device__ float predict(const Lds &s, const uint16_t *P)
 {
-    const int lane = threadIdx.x;
+    // opaque copies of the lane and the base: the weight addresses are then
+    // formed here, not hoisted out of the search loop into registers that
+    // would stay live (or spilled) through every expansion
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    asm volatile("" : "+s"(P));
     const uint16_t *W1 = P, *b1 = P + 1024, *W2 = P + 1088, *b2 = P + 5184, *w3 = P + 5248,
                    *b3 = P + 5312;
     float acc = bf16f(b1[lane]);
@@ -761,7 +853,9 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
     for (;;) {
         hint = first_unexpanded(s, hint, cnt);
         if (hint >= cnt || hops >= hopcap) break;
-        const int p = (int)(s.idf[hint] & kIdMask);
+        // the vertex to expand, the same in every lane: held in a scalar
+        // register, so its row's address costs no vector registers
+        const int p = __builtin_amdgcn_readfirstlane((int)(s.idf[hint] & kIdMask));
         __syncthreads();
         if (lane == 0) {
             s.idf[hint] |= kExpanded;
@@ -780,7 +874,8 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             int32_t u = -1;
             ItemAttr at;
             if (h + lane < a.R) {
-                u = row[h + lane];
+                u = *reinterpret_cast<const int32_t *>(reinterpret_cast<const unsigned char *>(row) +
+                                                       (uint32_t)(4 * (h + lane)));
                 load_row_attr<AK>(at, f, row, h + lane, a);
             }
             bool fresh = u >= 0 && hash_insert(s.hash, a.Hmask, u);
@@ -796,7 +891,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             }
             __syncthreads();
             if (m > 0) {
-                eval_rows<STORE, G, CH>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
+                eval_rows<STORE, G, CH, pair_rows<STORE, CH, AK>()>(a.vec, a.vec_stride, s.cid, s.cd2, m, qr);
                 __syncthreads();
                 ndist += m;
                 int mp = INT_MAX;
@@ -885,7 +980,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             s.cdf[lane] = (uint32_t)(s.key[lane] >> 32);
         }
         __syncthreads();
-        rerank_rows<STORE, G, CH>(a.f32, a.f32_stride, s.cid, s.cd2, rk, qr, a.d);
+        rerank_rows<STORE, G, CH, pair_rows<STORE, CH, AK>()>(a.f32, a.f32_stride, s.cid, s.cd2, rk, qr, qv, a.d);
         __syncthreads();
         uint64_t ck = 0;
         uint32_t ci = 0;

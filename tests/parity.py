@@ -43,12 +43,16 @@ def row_terms(store: int, d: int) -> tuple[int, int]:
 def lane_order(store: int, d: int) -> list[int]:
     """The oracle's contract-mode order for the GPU's row layout: (G lanes,
     elements per 16-byte chunk, chunks per lane) of the search store, then
-    of the FP32 rows the rerank reads, which the GPU splits over lanes as
-    it splits the store's rows (the same triple)."""
+    of the FP32 rows the rerank reads.  The GPU splits those over lanes as
+    it splits the store's rows (the same triple) when a lane's share is at
+    most 32 elements, else four lanes take the 16-byte pieces of the
+    64-byte-padded FP32 rows."""
     eb = {0: 4, 1: 2, 2: 1}[store]
     stride, G = _layout(eb * d + (4 if store == 2 else 0))
     out = [G, 16 // eb, stride // (16 * G)]
-    return out + out
+    if out[1] * out[2] <= 32:
+        return out + out
+    return out + [4, 4, _layout(4 * d)[0] // 64]
 
 
 def compare_strict(gpu_ids, gpu_d2, gpu_cnt, orc, what=""):
@@ -62,12 +66,13 @@ def compare_strict(gpu_ids, gpu_d2, gpu_cnt, orc, what=""):
 
 def tau_for(store: int, d: int, rerank_d: int | None = None) -> float:
     """tau for a search over `store` rows of d elements; with rerank_d, also
-    for the FP32 rescoring, whose rows the GPU splits over lanes as it
-    splits the store's (the same m and G per row)."""
+    for the FP32 rescoring (rows split as lane_order says)."""
     m, G = row_terms(store, d)
     eps = (m + 2 + math.log2(G)) * U
     if rerank_d is not None:
         m2, G2 = row_terms(store, rerank_d)
+        if m2 > 32:  # the four-lane layout of wide rows
+            m2, G2 = _layout(4 * rerank_d)[0] // 16, 4
         eps = max(eps, (m2 + 2 + math.log2(G2)) * U)
     tau = 2.02 * eps
     assert tau < 1e-5

@@ -7,11 +7,14 @@
 * the selectivity estimate in the filter records against the oracle's
   estimate (exact counts for label and range filters, label independence
   otherwise);
-* the predictor's features at the fourth expansion against the oracle's.
+* the predictor's features at the fourth expansion against the oracle's;
+* BF16 and FP8 rows whose lane share is wider than 32 elements (d = 160 and
+  150), where the FP32 rescoring switches to its four-lane layout.
 Each search is compared twice: with the FP64 oracle under the margin rule
 of tests/parity.py, and with the oracle's contract mode (FP32 distances in
 the kernel's documented lane order), where every query must return the same
 ids and bit-identical distances."""
+import dataclasses
 import sys
 
 import numpy as np
@@ -186,3 +189,43 @@ def test_slot_server_on_the_serving_shape(c5_shape):
         assert c == ref["count"][q] and np.array_equal(ids, ref["ids"][q]), q
         assert np.array_equal(d.view(np.uint32), ref["d2"][q].view(np.uint32)), q
     _say("slot server on the serving shape:", len(res), "answers equal")
+
+
+@pytest.fixture(scope="module")
+def wide_rows():
+    """4,000 points of the range recipe with vectors of 150 and 160
+    dimensions: BF16 rows of 320 bytes (five chunks per lane) and FP8 rows
+    of 154 bytes padded to 192 (three chunks of 16 codes), lane shares wide
+    enough that the FP32 rescoring takes its four-lane layout."""
+    from workloads.gen import mixture
+    w0 = make_config("c2", n=4000, nq=96)
+    out = {}
+    for d in (150, 160):
+        rng = np.random.default_rng(d)
+        X, C = mixture(rng, w0.X.shape[0], d, 32)
+        Q, _ = mixture(np.random.default_rng(d + 1), w0.Q.shape[0], d, 32, centers=C)
+        w = dataclasses.replace(w0, X=X, Q=Q)
+        adj, entry = jag.jag_build_graph(w.X, scalar=w.scalar, R=32,
+                                         thresholds=[(S, 1.0), (S, 0.01), (S, 0.0)], seed=3, device=True)
+        out[d] = (w, O.attrs_of(w), adj, entry)
+    return out
+
+
+@pytest.mark.parametrize("store,d", [(jag.STORE_BF16, 160), (jag.STORE_FP8_E4M3, 150)])
+def test_wide_rows_rescoring_matches_oracle(wide_rows, store, d):
+    w, A, adj, entry = wide_rows[d]
+    assert w.d == d
+    order = lane_order(store, d)
+    assert order[3:5] == [4, 4] and order[1] * order[2] > 32, order  # the four-lane rescoring layout
+    _say("wide rows store", store, "d", d)
+    idx = _index(w, adj, entry, store, keep_f32=True)
+    base = (O.bf16_decode(O.bf16_encode(w.X)) if store == jag.STORE_BF16
+            else O.fp8_decode_rows(*O.fp8_encode_rows(w.X)))
+    g = gpu_search(idx, w.Q, w.F, w.pool, 10, 48, rerank_mult=4)
+    orc = O.search(base, adj, entry, A, w.Q, w.F, w.pool, 48, 10, rerank=w.X, rerank_mult=4, nthreads=8)
+    n_ex, n_fl, n_fd = compare(g["ids"], g["d2"], g["count"], orc, tau_for(store, d, rerank_d=d),
+                               _valid_fn(w, w.F, w.pool), f"wide rows store={store} d={d}")
+    _say(f"exact {n_ex} flagged {n_fl} flagged-differing {n_fd}")
+    orc_c = O.search(base, adj, entry, A, w.Q, w.F, w.pool, 48, 10, rerank=w.X, rerank_mult=4, nthreads=8,
+                     contract=order)
+    compare_strict(g["ids"], g["d2"], g["count"], orc_c, f"wide rows store={store} d={d} (contract)")
