@@ -953,7 +953,12 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                     if (lane < 8) {
                         int v = lane == 0 ? idx + 1 : lane == 1 ? cnt : lane == 2 ? hint : lane == 3 ? hops
                               : lane == 4 ? ndist : lane == 5 ? nattr : lane == 6 ? hopcap : lhat;
-                        ws[lane] = v;
+                        // an opaque lane: the address is formed here, not
+                        // hoisted out of the search loop (where it would
+                        // sit in a spilled register pair)
+                        int ln = lane;
+                        asm volatile("" : "+v"(ln));
+                        ws[ln] = v;
                     }
                     if (lane == 0) a.order_key[q] = idx + 1;
                     return;
