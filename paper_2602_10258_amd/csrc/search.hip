@@ -154,11 +154,11 @@ __global__ void to_bf16_kernel(const float *x, int n, uint16_t *out)
 // records, so that the sort reads 4 bytes per query (one compute unit
 // reading every record line itself takes 35 us at 10,000 queries).
 // The sort is one workgroup; thread t owns queries t, t + 512, t + 1024,
-// ... (coalesced reads), taken 16 at a time so that 16 independent loads
+// ... (coalesced reads), taken 20 at a time so that 20 independent loads
 // are in flight per thread; within a class the order is (thread, then
 // position), not the query order, which no result depends on.
 constexpr int kOrderThreads = 512;
-constexpr int kOrderBatch = 16;
+constexpr int kOrderBatch = 20;
 constexpr int kOrderBins = JAG_LADDER_MAX + 1;
 // Fixed-beam and one-pass learned launches of at least this many queries
 // are ordered by selectivity (smaller ones fit on the device at once, where
@@ -187,15 +187,22 @@ __device__ __forceinline__ int order_class(const int32_t *key, int64_t i)
 }
 
 // Both loops clamp the index instead of branching on it, so that the
-// batch's loads issue back to back.
+// batch's loads issue back to back.  The counters are bumped with LDS
+// atomics (each thread owns its column, so nothing contends): one wave's
+// atomics run in program order, so the increments of a batch issue back to
+// back instead of as a chain of dependent reads and writes, and the ranks
+// come out as with plain increments.  A launch of at most kOrderThreads *
+// kOrderBatch queries (10,240) reads its classes once and keeps them in
+// registers for the second pass.
 __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key, int64_t nq, int32_t *perm)
 {
     __shared__ int32_t cnt[kOrderBins][kOrderThreads];
     __shared__ int32_t part[kOrderThreads];
     const int t = threadIdx.x;
     for (int b = 0; b < kOrderBins; b++) cnt[b][t] = 0;
+    const bool once = nq <= (int64_t)kOrderThreads * kOrderBatch;
+    int c[kOrderBatch];
     for (int64_t i0 = t; i0 < nq; i0 += (int64_t)kOrderThreads * kOrderBatch) {
-        int c[kOrderBatch];
 #pragma unroll
         for (int j = 0; j < kOrderBatch; j++) {
             const int64_t i = i0 + (int64_t)j * kOrderThreads;
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key
         }
 #pragma unroll
         for (int j = 0; j < kOrderBatch; j++)
-            if (i0 + (int64_t)j * kOrderThreads < nq) cnt[c[j]][t]++;
+            if (i0 + (int64_t)j * kOrderThreads < nq) atomicAdd(&cnt[c[j]][t], 1);
     }
     __syncthreads();
     // output rank r enumerates (bin descending, thread ascending); thread t
@@ -232,16 +239,17 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key
     }
     __syncthreads();
     for (int64_t i0 = t; i0 < nq; i0 += (int64_t)kOrderThreads * kOrderBatch) {
-        int c[kOrderBatch];
+        if (!once) {
 #pragma unroll
-        for (int j = 0; j < kOrderBatch; j++) {
-            const int64_t i = i0 + (int64_t)j * kOrderThreads;
-            c[j] = order_class(key, i < nq ? i : nq - 1);
+            for (int j = 0; j < kOrderBatch; j++) {
+                const int64_t i = i0 + (int64_t)j * kOrderThreads;
+                c[j] = order_class(key, i < nq ? i : nq - 1);
+            }
         }
 #pragma unroll
         for (int j = 0; j < kOrderBatch; j++) {
             const int64_t i = i0 + (int64_t)j * kOrderThreads;
-            if (i < nq) perm[cnt[c[j]][t]++] = (int32_t)i;
+            if (i < nq) perm[atomicAdd(&cnt[c[j]][t], 1)] = (int32_t)i;
         }
     }
 }
