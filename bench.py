@@ -697,16 +697,18 @@ class Leg:
             curve.sort(key=lambda r: r["L"])
         return curve
 
-    def learned_sweep(self, ntrain, L95, ladder_top=None, dump=None):
+    def learned_sweep(self, ntrain, L95, ladder_top=None, dump=None, ix=None, tag="bf16"):
         """Fit the predictor on a separate query set of this filter type and
         sweep its offset; the narrowest ladder whose sweep reaches 0.95.  Both
         target rules for training queries that never reach 0.95 (the widest
         beam, or the beam where their recall peaks) are fitted and swept; the
-        one with the higher QPS at 0.95 stays attached to the index."""
+        one with the higher QPS at 0.95 stays attached to the index (``ix``,
+        the BF16 index by default)."""
         from paper_2602_10258_amd import jag
         from paper_2602_10258_amd import predictor as pred
         from workloads.gen import extra_queries
         cfg = self.cfg
+        ix = cfg.ix16 if ix is None else ix
         t3 = time.time()
         Qt, Ft, pt = extra_queries(cfg.w, ntrain * (2 if cfg.name == "c3" else 4 if cfg.name == "c5" else 1),
                                    qseed=1000)
@@ -718,16 +720,16 @@ class Leg:
             for top in ladder_tops(L95, ladder_top):
                 lad = learned_ladder(L95, top)
                 log(f"{self.tag()} learned ladder {lad.tolist()}, unreachable targets: {rule}")
-                P, rho, rep = pred.fit(cfg.ix16, Qt, Ft, pt, k=self.k, exact_idx=cfg.ix32, rerank_mult=4,
+                P, rho, rep = pred.fit(ix, Qt, Ft, pt, k=self.k, exact_idx=cfg.ix32, rerank_mult=4,
                                        dump=dump, ladder=lad, unreachable=rule)
                 log(f"{self.tag()} predictor fitted on {rep.n_train} traces in {time.time() - t3:.1f}s: loss "
                     f"{rep.loss_first:.3f} -> {rep.loss_last:.3f}, rho={rho:.2f}, unreachable={rep.unreachable}")
                 learned = []
                 for delta in [-1.0, -0.5, 0.0, 0.5, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 6.0]:
-                    r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=delta, rerank_mult=4))
+                    r = self.point(ix, jag.SearchParams(L=self.k, learned=1, delta=delta, rerank_mult=4))
                     r["delta"] = delta
                     learned.append(r)
-                    log(f"{self.tag()} learned+bf16 delta={delta:+.2f} recall={r['recall']:.4f} "
+                    log(f"{self.tag()} learned+{tag} delta={delta:+.2f} recall={r['recall']:.4f} "
                         f"qps={r['qps']:.0f} mean Lhat={r['lhat']:.1f}")
                     if r["recall"] >= 0.995 or (r["recall"] >= 0.95 and delta >= 1.0):
                         break
@@ -740,7 +742,7 @@ class Leg:
                 lo, hi = learned[j - 1]["delta"], learned[j]["delta"]
                 for _ in range(4):
                     mid = round((lo + hi) / 2, 4)
-                    r = self.point(cfg.ix16, jag.SearchParams(L=self.k, learned=1, delta=mid, rerank_mult=4))
+                    r = self.point(ix, jag.SearchParams(L=self.k, learned=1, delta=mid, rerank_mult=4))
                     r["delta"] = mid
                     learned.append(r)
                     log(f"{self.tag()}   refine delta={mid:+.4f} recall={r['recall']:.4f} qps={r['qps']:.0f}")
@@ -756,10 +758,11 @@ class Leg:
         rule = max(runs, key=lambda r: score(runs[r]))
         learned, lad, rep, P, rho = runs[rule]
         if P is not None:
-            jag.jag_set_predictor(cfg.ix16, P, np.maximum(lad, self.k), rho)
-        self.target_rules = {r: round(score(v), 1) if score(v) > 0 else None for r, v in runs.items()}
-        self.target_rule = rule
-        log(f"{self.tag()} QPS at 0.95 by target rule: {self.target_rules}; keeping {rule}")
+            jag.jag_set_predictor(ix, P, np.maximum(lad, self.k), rho)
+        rules = {r: round(score(v), 1) if score(v) > 0 else None for r, v in runs.items()}
+        if tag == "bf16":
+            self.target_rules, self.target_rule = rules, rule
+        log(f"{self.tag()} learned+{tag} QPS at 0.95 by target rule: {rules}; keeping {rule}")
         return learned, lad, rep
 
     def tag(self):
@@ -857,6 +860,9 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
                                  beams=[L for L in LADDER_FIXED if L95 / 2 <= L <= 2 * L95])
     learned, lad, rep = ([], None, None) if args.only_fixed else leg.learned_sweep(
         args.ntrain, L95, args.ladder_top, args.dump_traces if headline else None)
+    # the learned beam over the FP8 store too, where the FP8 fixed beam was swept
+    learned8 = [] if args.only_fixed or not fixed8 else leg.learned_sweep(
+        args.ntrain, L95, args.ladder_top, None, ix=cfg.ix8(), tag="fp8")[0]
     best_f, interp_f = at95(fixed)
     best_16, interp_16 = at95(fixed16)
     best_8, interp_8 = at95(fixed8) if fixed8 else (None, None)
@@ -896,6 +902,8 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
                "bf16_rerank_fixed": best_16 and round(best_16["qps"], 1), "bf16_rerank_fixed_L": best_16 and best_16["L"],
                "bf16_rerank_fixed_interp": interp_16 and round(interp_16, 1),
                "fp8_rerank_fixed": best_8 and round(best_8["qps"], 1), "fp8_rerank_fixed_L": best_8 and best_8["L"],
+               "learned_fp8_rerank": (at95(learned8)[0] or {}).get("qps") and round(at95(learned8)[0]["qps"], 1),
+               "learned_fp8_delta": (at95(learned8)[0] or {}).get("delta"),
                "learned_bf16_rerank": best_l and round(best_l["qps"], 1),
                "learned_bf16_rerank_interp": interp_l and round(interp_l, 1),
                "learned_delta": best_l and best_l["delta"], "learned_mean_beam": best_l and round(best_l["lhat"], 2)},
@@ -909,7 +917,8 @@ def run_leg(args, cfg: Config, ftype: int, timer, headline: bool):
            "selectivity_estimate": leg.selectivity_accuracy(),
            "graph_build_seconds": cfg.build_times,
            "sweeps": {"fp32_fixed": [rounded(r) for r in fixed], "bf16_rerank_fixed": [rounded(r) for r in fixed16],
-                      "fp8_rerank_fixed": [rounded(r) for r in fixed8], "learned": [rounded(r) for r in learned]}}
+                      "fp8_rerank_fixed": [rounded(r) for r in fixed8], "learned": [rounded(r) for r in learned],
+                      "learned_fp8": [rounded(r) for r in learned8]}}
     if not cands:
         top = max(fixed + fixed16 + learned, key=lambda r: r["recall"])
         out["note"] = "no configuration reached recall@10 = 0.95"
@@ -1131,7 +1140,10 @@ def main():
                     "learned_over_fp32_fixed": v.get("learned_over_fp32_fixed"),
                     "learned_over_bf16_fixed": v.get("learned_over_bf16_fixed"),
                     "roofline_frac": v.get("roofline", {}).get("frac"), "end_to_end_qps": v.get("end_to_end_qps"),
-                    "kernel_qps": v.get("kernel_qps")} for k_, v in results.items()}
+                    "kernel_qps": v.get("kernel_qps"),
+                    **({"fp8_rerank_fixed": v["qps_at_095"]["fp8_rerank_fixed"],
+                        "learned_fp8_rerank": v["qps_at_095"]["learned_fp8_rerank"]}
+                       if v["qps_at_095"].get("learned_fp8_rerank") else {})} for k_, v in results.items()}
     out = {
         "metric": METRIC, "value": headline.get("value"), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": headline.get("ms_per_step"),

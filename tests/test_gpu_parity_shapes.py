@@ -229,3 +229,43 @@ def test_wide_rows_rescoring_matches_oracle(wide_rows, store, d):
     orc_c = O.search(base, adj, entry, A, w.Q, w.F, w.pool, 48, 10, rerank=w.X, rerank_mult=4, nthreads=8,
                      contract=order)
     compare_strict(g["ids"], g["d2"], g["count"], orc_c, f"wide rows store={store} d={d} (contract)")
+
+
+def test_learned_fp8_search_matches_oracle(c5_shape):
+    """The learned beam over the FP8 store with the FP32 rerank: the same BF16
+    network on both sides (the oracle evaluates it in FP64, so queries whose
+    y + delta lies within 1e-4 of an integer are left out), distances in the
+    kernel's lane order; where both pick the same beam every query returns
+    the same ids, distances and count, in one pass and in two."""
+    from .test_gpu_learned import _params
+    w, A, adj, entry = c5_shape
+    P = _params(13, scale=0.3)
+    Pq = O.bf16_decode(O.bf16_encode(P))
+    ladder = np.array([16, 24, 32, 48, 64, 96, 128], dtype=np.int32)
+    rho = 3.0
+    idx = _index(w, adj, entry, jag.STORE_FP8_E4M3, keep_f32=True)
+    jag.jag_set_predictor(idx, P, ladder, rho)
+    base = O.fp8_decode_rows(*O.fp8_encode_rows(w.X))
+    sf = O.sel_feature(O.selectivity(A, w.F, w.pool))
+    for delta in (0.0, 1.5):
+        # the first four expansions keep the widest beam's 128 entries on both sides
+        orc = O.search(base, adj, entry, A, w.Q, w.F, w.pool, 128, 10, rerank=w.X, rerank_mult=4,
+                       learned=Pq, delta=delta, rho=rho, ladder=ladder, sel_feature=sf, nthreads=8,
+                       contract=lane_order(jag.STORE_FP8_E4M3, w.d))
+        z = orc.y + delta
+        safe = np.abs(z - np.round(z)) > 1e-4
+        assert safe.mean() >= 0.9
+        for single in (1, 0):
+            _say("learned fp8 d=100 delta", delta, "single pass" if single else "two passes")
+            g = gpu_search(idx, w.Q, w.F, w.pool, 10, 16, learned=1, delta=delta, rerank_mult=4,
+                           single_pass=single)
+            lh = g["stats"][:, 3]
+            assert np.array_equal(lh[safe], orc.lhat[safe]), (delta, lh[safe][:10], orc.lhat[safe][:10])
+            assert np.array_equal(g["ids"][safe], orc.ids[safe])
+            assert np.array_equal(g["count"][safe], orc.count[safe])
+            for q in np.flatnonzero(safe):
+                c = int(g["count"][q])
+                assert np.array_equal(g["d2"][q, :c].astype(np.float64), orc.d2[q, :c]), q
+            assert np.array_equal(g["stats"][safe, 0], orc.hops[safe])
+        _say(f"delta={delta}: {safe.sum()} of {w.nq} queries compared; beams "
+             f"{np.bincount(lh, minlength=int(ladder[-1]) + 1)[ladder].tolist()}")
