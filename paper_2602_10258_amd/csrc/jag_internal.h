@@ -94,6 +94,11 @@ struct Index {
     int64_t device_bytes = 0;
     Predictor pred;
     StagingRing *staging = nullptr;
+    // Launch order statistics (search.hip): per filter kind (range, other)
+    // and selectivity class, the sum of expansions and the number of
+    // searches of the index's one-pass learned launches, older launches
+    // weighing half per launch.
+    unsigned long long *d_order_stats = nullptr;
 };
 
 // Number of items whose scalar is below v (exact; the rank index narrows

@@ -170,14 +170,57 @@ static bool sel_ordered(const jag_search_params &S, int64_t nq)
     return (S.learned == 0 || (S.learned == 1 && S.single_pass)) && nq >= kSelOrderMin;
 }
 
-__global__ __launch_bounds__(256) void class_kernel(const FilterRecord *rec, int64_t nq, int32_t *key)
+// Range filters in one-pass learned launches: once the index's own such
+// launches have run enough searches of a class (kMinClassRuns), the class
+// ranks by its mean expansions instead: key = 16 * mean / (largest mean
+// over the range classes with data), so that the classes that searched
+// longest run first whatever shape the relation to selectivity takes (on
+// the range workload it is not monotonic: the broadest and the middle
+// classes search longest).  Range classes without data take the mean over
+// those with data; with no data at all the fixed rank above applies.
+// Label-based filters keep the fixed rank (narrowest first measured 10 %
+// faster than the learned rank for one-pass subset searches).
+// order_kernel halves the sums and counts before each such launch adds its
+// own, so the ranking follows the recent launches (a sweep over offsets
+// does not freeze it).
+constexpr unsigned long long kMinClassRuns = 64;
+
+__global__ __launch_bounds__(256) void class_kernel(const FilterRecord *rec, int64_t nq, int32_t *key,
+                                                    const unsigned long long *stats)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ float mean[2 * kSelClasses];
+    __shared__ float top, avg;
+    const int t = threadIdx.x;
+    if (stats) {
+        if (t < 2 * kSelClasses) {
+            const unsigned long long n = stats[2 * t + 1];
+            mean[t] = n >= kMinClassRuns ? (float)stats[2 * t] / (float)n : -1.f;
+        }
+        __syncthreads();
+        if (t == 0) {
+            float hi = 0.f, sum = 0.f;
+            int with = 0;
+            for (int c = 0; c < kSelClasses; c++)  // the range classes
+                if (mean[c] >= 0.f) {
+                    hi = mean[c] > hi ? mean[c] : hi;
+                    sum += mean[c];
+                    with++;
+                }
+            top = hi;
+            avg = with ? sum / (float)with : 0.f;
+        }
+        __syncthreads();
+    }
+    const int64_t i = (int64_t)blockIdx.x * 256 + t;
     if (i >= nq) return;
-    const float x = rec[i].sel_feature;  // log2(selectivity) / 16, in [-1.9, 0]
-    const float c = floorf(16.f + x * (256.f / 30.f));
-    const int broad = c >= 0.f ? (c <= 16.f ? (int)c : 16) : 0;  // 16: selectivity 1
-    key[i] = rec[i].type == F_RANGE ? broad : 16 - broad;
+    const int kind = sel_kind(rec[i].type), broad = sel_class(rec[i].sel_feature);  // 16: selectivity 1
+    int k = kind == 0 ? broad : 16 - broad;
+    if (stats && kind == 0 && top > 0.f) {
+        const float m = mean[broad];
+        const int b = (int)(16.f * (m >= 0.f ? m : avg) / top);
+        k = b < 0 ? 0 : (b > 16 ? 16 : b);
+    }
+    key[i] = k;
 }
 
 __device__ __forceinline__ int order_class(const int32_t *key, int64_t i)
@@ -194,11 +237,13 @@ __device__ __forceinline__ int order_class(const int32_t *key, int64_t i)
 // come out as with plain increments.  A launch of at most kOrderThreads *
 // kOrderBatch queries (10,240) reads its classes once and keeps them in
 // registers for the second pass.
-__global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key, int64_t nq, int32_t *perm)
+__global__ __launch_bounds__(kOrderThreads) void order_kernel(const int32_t *key, int64_t nq, int32_t *perm,
+                                                              unsigned long long *stats)
 {
     __shared__ int32_t cnt[kOrderBins][kOrderThreads];
     __shared__ int32_t part[kOrderThreads];
     const int t = threadIdx.x;
+    if (stats && t < 4 * kSelClasses) stats[t] >>= 1;  // older launches weigh half
     for (int b = 0; b < kOrderBins; b++) cnt[b][t] = 0;
     const bool once = nq <= (int64_t)kOrderThreads * kOrderBatch;
     int c[kOrderBatch];
@@ -475,6 +520,11 @@ jag_status upload_index(Index &ix)
         set_error("store layout kernels failed: %s", hipGetErrorString(e));
         return JAG_EDEVICE;
     }
+    if (!ix.d_order_stats) {
+        const size_t sb = sizeof(unsigned long long) * 4 * kSelClasses;
+        if ((st = dalloc(&ix.d_order_stats, sb, ix.device_bytes)) != JAG_OK) return st;
+        HIPCHK(hipMemset(ix.d_order_stats, 0, sb));
+    }
     return JAG_OK;
 }
 
@@ -491,6 +541,8 @@ void free_device(Index &ix)
     if (ix.f32_owned) f(ix.d_f32);
     f(ix.d_vec);
     f(ix.pred.d_bf16);
+    f(ix.d_order_stats);
+    ix.d_order_stats = nullptr;
     ix.d_adj = nullptr;
     ix.d_scalar = nullptr;
     ix.d_lab = nullptr;
@@ -567,6 +619,7 @@ static jag_status fill_args(Index &ix, SearchArgs &a, const float *Q, const void
     a.state = nullptr;
     a.state_stride = 0;
     a.order_key = nullptr;
+    a.order_stats = nullptr;
     return JAG_OK;
 }
 
@@ -687,17 +740,24 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         }
     }
     if (order) {
-        // one launch, the searches expected to be long first
+        // one launch, the searches expected to be long first; one-pass
+        // learned launches rank range filters' classes by what the index's
+        // earlier one-pass launches measured (fixed-beam launches keep the
+        // fixed rank, which measured 10 % faster for them than this one on
+        // the range workload)
+        unsigned long long *st = S.learned == 1 ? ix.d_order_stats : nullptr;
         int32_t *key = order + nq;
-        hipLaunchKernelGGL(class_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, sm, a.rec, nq, key);
+        hipLaunchKernelGGL(class_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, sm, a.rec, nq, key,
+                           (const unsigned long long *)st);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, key, nq, order);
+            hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, key, nq, order, st);
             e = hipGetLastError();
         }
         if (e == hipSuccess) {
             SearchArgs b = a;
             b.perm = order;
+            b.order_stats = st;
             hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, sm, b);
             e = hipGetLastError();
         }
@@ -753,7 +813,8 @@ jag_status launch_search(Index &ix, const float *Q, int64_t nq, const void *reco
         hipLaunchKernelGGL(fn, dim3((unsigned)nc), dim3(64), lds, sm, b3);
         e = hipGetLastError();
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, okey, nc, perm);
+        hipLaunchKernelGGL(order_kernel, dim3(1), dim3(kOrderThreads), 0, sm, okey, nc, perm,
+                           (unsigned long long *)nullptr);
         e = hipGetLastError();
         if (e != hipSuccess) break;
         b.mode = 4;

@@ -53,10 +53,24 @@ struct SearchArgs {
     const int32_t *perm;  // query handled by each workgroup (null: identity)
     int32_t *state;       // modes 3 and 4: saved search state, state_stride words per query
     int32_t *order_key;   // mode 3: 1 + predicted ladder index per query (0: ended before)
+    // ordered launches: per (filter kind, selectivity class), the sum of
+    // expansions and the count of searches (null: not recorded)
+    unsigned long long *order_stats;
     int64_t state_stride;
     float delta, rho;
     int32_t ladder[JAG_LADDER_MAX];
 };
+
+// Selectivity class of a filter record for the launch order: its log2
+// selectivity estimate in steps of about two octaves (0 = narrowest, 16 =
+// selectivity 1), and its kind (0 range, 1 the label-based filters).
+constexpr int kSelClasses = 17;
+__host__ __device__ inline int sel_class(float sel_feature)
+{
+    const float c = floorf(16.f + sel_feature * (256.f / 30.f));  // sel_feature = log2(s) / 16
+    return c >= 0.f ? (c <= 16.f ? (int)c : 16) : 0;
+}
+__host__ __device__ inline int sel_kind(int32_t type) { return type == F_RANGE ? 0 : 1; }
 
 // Which attributes an index's items carry; kernels are built per kind so
 // that an index with scalars only (range filters) or labels only carries no
@@ -786,7 +800,7 @@ __device__ float predict(const Lds &s, const uint16_t *P)
 // (stats, features, saved states, launch order).  SL: 64-neighbour slices per
 // row (2 for R up to 128); AK: AttrKind.
 template <int STORE, int G, int CH, int SL, int AK>
-__device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t q, const FilterRecord &f,
+__device__ __forceinline__ int search_query(const SearchArgs &a, const int64_t q, const FilterRecord &f,
                                              const uint8_t *tab, const float *qv, int32_t *ids_out,
                                              float *dists_out, int32_t *count_out, unsigned char *smem)
 {
@@ -961,7 +975,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
                         ws[ln] = v;
                     }
                     if (lane == 0) a.order_key[q] = idx + 1;
-                    return;
+                    return hops;
                 }
             }
         }
@@ -973,7 +987,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             a.state[q * a.state_stride] = 0;
             a.order_key[q] = 0;
         }
-        return;
+        return hops;
     }
     // ---- output: top-k valid entries, optionally rescored in FP32
     int outn = cnt;
@@ -1021,6 +1035,7 @@ __device__ __forceinline__ void search_query(const SearchArgs &a, const int64_t 
             a.stats[q * 4 + 3] = lhat;
         }
     }
+    return hops;
 }
 
 // WPE: occupancy target (waves per SIMD) the register allocator works to.
@@ -1033,8 +1048,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const FilterRecord f = a.rec[q];
     // TABLE filters: the distance table sits table_off bytes after the record
     const uint8_t *tab = f.type == F_TABLE ? reinterpret_cast<const uint8_t *>(a.rec + q) + f.table_off : nullptr;
-    search_query<STORE, G, CH, SL, AK>(a, q, f, tab, a.Q + q * a.d, a.ids + q * a.k, a.dists + q * a.k,
-                                       a.count + q, smem);
+    const int hops = search_query<STORE, G, CH, SL, AK>(a, q, f, tab, a.Q + q * a.d, a.ids + q * a.k,
+                                                        a.dists + q * a.k, a.count + q, smem);
+    if (a.order_stats && threadIdx.x == 0) {  // what the next ordered launches rank classes by
+        const int c = sel_kind(f.type) * kSelClasses + sel_class(f.sel_feature);
+        atomicAdd(a.order_stats + 2 * c, (unsigned long long)hops);
+        atomicAdd(a.order_stats + 2 * c + 1, 1ull);
+    }
 }
 
 // Lanes per vector row: 4 for rows of up to 384 bytes, 8 up to 512 bytes,
